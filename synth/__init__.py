@@ -1,0 +1,184 @@
+"""Seeded synthetic inputs for the point -> block mapping workloads.
+
+Generates watertight block partitions, their group hierarchy and query points.
+Inputs only: nothing here computes bounding boxes or crossing tests, so the GPU
+library and the CPU oracle can both consume these arrays without sharing any of
+the mapping arithmetic. The arrays stand in for the census shapefiles and the
+mobile-location points of the paper (Sec. II, Sec. V), which are not available.
+
+The heavy lifting is in ``synth.c`` (counter-based splitmix64 streams, OpenMP),
+built into ``libsynth.so`` next to this file.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsynth.so")
+SEED = 200503156
+
+
+def build(force: bool = False) -> str:
+    """Compile libsynth.so with gcc (OpenMP, no FP contraction)."""
+    src = os.path.join(_HERE, "synth.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = C.CDLL(_LIB_PATH)
+        u64, i64, i32, dbl, P = C.c_uint64, C.c_int64, C.c_int32, C.c_double, C.c_void_p
+        lib.syn_key.restype = u64
+        lib.syn_key.argtypes = [u64, u64, u64, u64]
+        lib.syn_rand_u64.restype = u64
+        lib.syn_rand_u64.argtypes = [u64, u64]
+        lib.syn_rand_u01.restype = dbl
+        lib.syn_rand_u01.argtypes = [u64, u64]
+        lib.syn_grid_offsets.restype = i64
+        lib.syn_grid_offsets.argtypes = [P, P]
+        lib.syn_grid_fill.restype = None
+        lib.syn_grid_fill.argtypes = [P, P, P]
+        lib.syn_band_hierarchy.restype = None
+        lib.syn_band_hierarchy.argtypes = [i32, i32, P, P, P]
+        lib.syn_mixture_setup.restype = None
+        lib.syn_mixture_setup.argtypes = [u64, i32, dbl, dbl, dbl, dbl, P, P, P, P]
+        lib.syn_mixture_points.restype = None
+        lib.syn_mixture_points.argtypes = [u64, i64, i64, i32, P, P, P, P, dbl, dbl, dbl, P]
+        lib.syn_sizes.restype = None
+        lib.syn_sizes.argtypes = [u64, i64, i32, dbl, dbl, dbl, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def key(cfg: int, stream: int, k: int = 0) -> int:
+    return int(_L().syn_key(SEED, cfg, stream, k))
+
+
+class _GridParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("c", C.c_int64), ("klaw", C.c_int32), ("kmin", C.c_int32),
+                ("kmax", C.c_int32), ("kp", C.c_double), ("vjit", C.c_double), ("pjit", C.c_double),
+                ("taper", C.c_double), ("key", C.c_uint64)]
+
+
+@dataclass
+class Geometry:
+    """A block partition plus its hierarchy.
+
+    vert_off: int64 [n_blocks+1]; ring b is verts[vert_off[b]:vert_off[b+1]] (no closing duplicate)
+    verts:    int32 [V, 2] (x, y)
+    n_groups: group counts per level, coarse -> fine (blocks excluded)
+    parents:  parents[l][i] = level-l group of entity i of level l+1 (blocks for the last)
+    W:        the partition covers exactly [0, W)^2 (see the generator)
+    """
+    vert_off: np.ndarray
+    verts: np.ndarray
+    n_groups: list
+    parents: list
+    W: int
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_blocks(self) -> int:
+        return int(self.vert_off.shape[0] - 1)
+
+
+def jittered_grid(n: int, c: int, *, klaw: int = 0, kmin: int = 3, kmax: int = 6, kp: float = 0.25,
+                  vjit: float = 0.3, pjit: float = 0.1, taper: float = 0.2, key_: int = 1):
+    """Shared-edge jittered grid: n x n blocks over [0, n*c]^2, block id = row*n + col."""
+    g = _GridParams(n, c, klaw, kmin, kmax, kp, vjit, pjit, taper, key_)
+    off = np.empty(n * n + 1, np.int64)
+    total = _L().syn_grid_offsets(C.byref(g), _p(off))
+    verts = np.empty((total, 2), np.int32)
+    _L().syn_grid_fill(C.byref(g), _p(off), _p(verts))
+    return off, verts
+
+
+def band_hierarchy(n: int, bands):
+    """Nested bands: bands = [(rows, cols), ...] coarse -> fine."""
+    L = len(bands)
+    rows = np.array([b[0] for b in bands], np.int32)
+    cols = np.array([b[1] for b in bands], np.int32)
+    sizes = [bands[l + 1][0] * bands[l + 1][1] for l in range(L - 1)] + [n * n]
+    parents = [np.empty(s, np.int32) for s in sizes]
+    arr = (C.c_void_p * L)(*[p.ctypes.data for p in parents])
+    _L().syn_band_hierarchy(n, L, _p(rows), _p(cols), arr)
+    return [int(r * c) for r, c in bands], parents
+
+
+# ------------------------------------------------------------ the configs ----
+
+# config 1: 32 x 32 jittered grid over [0, 1e6]^2, 3..6 points per shared edge,
+# 8 x 8 groups of 4 x 4 blocks; 100,000 points.
+# config 2: 470 x 470 grid (220,900 blocks), 2 + Geometric(1/4) (<= 40) points
+# per edge; 50 regions / 3,000 counties / 70,000 tracts; 100M points.
+CONFIGS = {
+    1: dict(n=32, c=31_250, klaw=0, kmin=3, kmax=6, kp=0.0, bands=[(8, 8)], n_points=100_000,
+            K=5, wsig=0.0, sig=(0.05, 0.05), p_unif=0.20),
+    2: dict(n=470, c=2_000_000, klaw=1, kmin=2, kmax=40, kp=0.25,
+            bands=[(5, 10), (50, 60), (250, 280)], n_points=100_000_000,
+            K=200, wsig=1.0, sig=(0.005, 0.05), p_unif=0.05),
+}
+
+
+def geometry(cfg: int) -> Geometry:
+    p = CONFIGS[cfg]
+    off, verts = jittered_grid(p["n"], p["c"], klaw=p["klaw"], kmin=p["kmin"], kmax=p["kmax"],
+                               kp=p["kp"], key_=key(cfg, 0, 0))
+    n_groups, parents = band_hierarchy(p["n"], p["bands"])
+    return Geometry(off, verts, n_groups, parents, W=p["n"] * p["c"], name="config%d" % cfg,
+                    meta=dict(grid_n=p["n"], cell=p["c"]))
+
+
+class Mixture:
+    """Gaussian mixture plus a uniform share over the 10%-enlarged extent."""
+
+    def __init__(self, key_: int, K: int, W: float, wsig: float, sig_lo: float, sig_hi: float,
+                 p_unif: float):
+        self.K, self.W, self.p_unif = K, W, p_unif
+        self.cumw, self.cx, self.cy, self.sig = (np.empty(K) for _ in range(4))
+        _L().syn_mixture_setup(key_, K, W, wsig, sig_lo, sig_hi, _p(self.cumw), _p(self.cx),
+                               _p(self.cy), _p(self.sig))
+
+    def sample(self, key_: int, i0: int, n: int, out: np.ndarray | None = None) -> np.ndarray:
+        out = np.empty((n, 2), np.int32) if out is None else out
+        assert out.shape == (n, 2) and out.dtype == np.int32 and out.flags.c_contiguous
+        lo, hi = -0.05 * self.W, 1.05 * self.W
+        _L().syn_mixture_points(key_, i0, n, self.K, _p(self.cumw), _p(self.cx), _p(self.cy),
+                                _p(self.sig), self.p_unif, lo, hi, _p(out))
+        return out
+
+
+def points(cfg: int, n: int | None = None, i0: int = 0, out: np.ndarray | None = None) -> np.ndarray:
+    """Points i0 .. i0+n-1 of a config's point stream (int32 [n, 2])."""
+    p = CONFIGS[cfg]
+    W = p["n"] * p["c"]
+    n = p["n_points"] if n is None else n
+    m = Mixture(key(cfg, 1, 0), p["K"], W, p["wsig"], p["sig"][0], p["sig"][1], p["p_unif"])
+    return m.sample(key(cfg, 1, 1), i0, n, out)
+
+
+def sizes(key_: int, nb: int, law: int, median: float, s: float, hi: float) -> np.ndarray:
+    out = np.empty(nb, np.int64)
+    _L().syn_sizes(key_, nb, law, median, s, hi, _p(out))
+    return out
