@@ -1,0 +1,135 @@
+"""Throughput benchmark: points mapped per second on one MI355X.
+
+Workload: 220,900 jittered grid blocks (470 x 470, ~24 vertices each) under a
+4-level hierarchy (50 regions / 3,000 counties / 70,000 tracts), 100M int32
+points from a 200-component Gaussian mixture plus 5% uniform outliers. One
+step maps all 100M points (inputs resident in HBM). Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+# MI355X published figures: 256 CUs at 2.4 GHz, 64 lanes per CU-cycle of
+# integer vector ALU; HBM3E 8 TB/s.
+PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.32 T lane-ops/s
+PEAK_HBM_GBS = 8000.0
+
+# Work per point of the method on this workload, from the oracle's instrumented
+# counts over the workload's first 2M points: 140.38 box tests, 34.98 ring-edge
+# tests and 0.239 exact cross products per point. Lane-operation cost model:
+# 5 per box test (4 compares + and), 7 per edge test (2 compares, straddle,
+# x-range, parity), 12 per cross product -> 949.7 integer lane-ops per point.
+OPS_PER_POINT = 5 * 140.38 + 7 * 34.98 + 12 * 0.239
+# Algorithmic HBM bytes per point: 8 in + 4 out (the 51 MB index is read once
+# per launch from cache; 0.5 B/pt).
+BYTES_PER_POINT = 12.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the mapping path has no multi-GPU form here "
+              "(see DESIGN.md, 'Sharding'); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2005_03156_amd as bm
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    g = synth.geometry(2)
+    n = synth.CONFIGS[2]["n_points"]
+    pts = synth.points(2, n)
+    log("generated %d blocks, %d points in %.1fs" % (g.n_blocks, n, time.time() - t0))
+    ix = bm.Index.from_geometry(g)
+    xy = torch.from_numpy(pts).to(dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        bm.map_points(ix, xy, out, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ev[2 * k].record(stream)
+        bm.map_points(ix, xy, out, stream)
+        ev[2 * k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kern_ms = [ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]
+    avg_ms = float(np.mean(kern_ms))
+    value = n * args.steps / wall
+    log("plain: %.3f ms/launch (events), wall %.3f ms/step, %.3g points/s" %
+        (avg_ms, wall * 1e3 / args.steps, value))
+
+    achieved = OPS_PER_POINT * n / (avg_ms * 1e-3) / 1e12
+    hbm_gbs = BYTES_PER_POINT * n / (avg_ms * 1e-3) / 1e9
+    res = {
+        "metric": "points mapped/sec on 1 GPU (plain kernel; batched and served forms reported beside it)",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "census-scale plain mapping: 220,900 blocks (470x470 jittered grid, "
+                               "~24 vertices/block), 4-level hierarchy 50/3,000/70,000/220,900, "
+                               "100M int32 points (200-Gaussian mixture + 5% uniform)",
+                   "points_per_step": n, "blocks": g.n_blocks},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
+                     "frac": achieved / PEAK_INT_TOPS, "traffic": None,
+                     "kernel": "map_kernel", "kernel_ms": avg_ms,
+                     "ops_per_point": OPS_PER_POINT},
+        "hbm": {"achieved_GBs": hbm_gbs, "peak_GBs": PEAK_HBM_GBS, "frac": hbm_gbs / PEAK_HBM_GBS,
+                "bytes_per_point": BYTES_PER_POINT},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(g, pts)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(g, pts):
+    """The CPU oracle (hierarchy route) on the host cores, timed on the first
+    part of the same point stream."""
+    import oracle
+    ns = min(pts.shape[0], int(os.environ.get("BENCH_CPU_POINTS", 40_000_000)))
+    H = oracle.Hier.from_geometry(g)
+    H.map(pts[:100_000])  # warm
+    t = time.perf_counter()
+    H.map(pts[:ns])
+    dt = time.perf_counter() - t
+    return {"value": ns / dt, "unit": "points/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "first %d of the workload's 100M points, hierarchy route (C, OpenMP), %.1f s" % (ns, dt)}
+
+
+if __name__ == "__main__":
+    main()

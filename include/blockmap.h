@@ -1,0 +1,171 @@
+/*
+ * blockmap -- map points onto the blocks of a polygon partition on an AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation (paper: "Fast Mapping onto Census Blocks", Sec. III and
+ * Sec. III-A): for every query point, find the block whose polygon contains
+ * it. Candidates are narrowed with a hierarchy of bounding boxes (groups of
+ * blocks, groups of groups, ...), and every surviving block is decided with
+ * the crossing-number test: the number of times a ray from the point towards
+ * +x crosses the block's boundary is odd exactly when the point is inside.
+ *
+ * Exactness. Coordinates are integers and every decision is exact:
+ *   - an edge (a -> b) takes part when exactly one end lies strictly above the
+ *     point (a.y > p.y differs from b.y > p.y); horizontal edges never do;
+ *   - it counts when it meets the point's horizontal line strictly to the
+ *     right of the point, decided with exact 64-bit integer products;
+ *   - so a point on a boundary belongs to the block on its right (and, on a
+ *     horizontal boundary, to the block above it). In a gap-free partition of
+ *     the plane every point lies in exactly one block;
+ *   - bounding boxes are half-open, [xmin, xmax) x [ymin, ymax), which never
+ *     drops a containing block;
+ *   - when several blocks contain a point (overlapping input) the answer is
+ *     the smallest block index; when none does it is -1.
+ *
+ * All entry points return a status code (BM_OK on success); no C++ exception
+ * crosses this interface. bm_last_error() gives a description of the last
+ * failure on the calling thread.
+ */
+#ifndef BLOCKMAP_H
+#define BLOCKMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The HIP stream type, declared exactly as the HIP runtime declares it. */
+typedef struct ihipStream_t* hipStream_t;
+
+enum {
+  BM_OK = 0,
+  BM_EINVAL = 1,     /* bad argument: null pointer, negative size, bad descriptor */
+  BM_ERANGE = 2,     /* a vertex coordinate outside [0, 2^31 - 1], or an index too large */
+  BM_ENOMEM = 3,     /* a device or host allocation failed */
+  BM_EHIP = 4,       /* the HIP runtime reported an error */
+  BM_EBUSY = 5,      /* the server queue is full */
+  BM_ETIMEDOUT = 6,  /* a wait ran out of time */
+  BM_EIO = 7         /* a file could not be read or written */
+};
+
+/* ------------------------------------------------------------------------ */
+/* Index: the blocks and their group hierarchy, resident in device memory.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct bm_index bm_index;
+
+/* Host-side description of a partition and its hierarchy (paper Sec. III-B:
+ * state -> county -> block, here any number of group levels).
+ *
+ *   n_blocks      number of blocks (at most 2^31 - 1). Block b keeps the index b
+ *                 in every result.
+ *   vert_off      [n_blocks + 1] int64, vert_off[0] = 0, non-decreasing: ring b
+ *                 is verts_xy[2*vert_off[b] .. 2*vert_off[b+1]).
+ *   verts_xy      interleaved (x, y) int32 vertices, each coordinate in
+ *                 [0, 2^31 - 1]. A ring is closed implicitly from its last
+ *                 vertex to its first; a stored closing copy of the first
+ *                 vertex is harmless. Every ring has at least 3 vertices.
+ *                 Holes or several parts can be joined into one ring by a
+ *                 bridge walked once each way (its crossings cancel).
+ *   n_levels      number of group levels above the blocks (0 = no hierarchy).
+ *   n_groups      [n_levels] group count per level, coarse to fine (each >= 1).
+ *   parent        [n_levels] arrays: parent[l][i] in [0, n_groups[l]) is the
+ *                 level-l group of entity i of level l+1 (of block i for
+ *                 l = n_levels - 1). Groups may be empty. Any grouping gives
+ *                 the same result; a spatially tight one is faster.
+ *
+ * The descriptor and its arrays are only read during bm_index_create. */
+typedef struct {
+  int64_t n_blocks;
+  const int64_t* vert_off;
+  const int32_t* verts_xy;
+  int32_t n_levels;
+  const int64_t* n_groups;
+  const int32_t* const* parent;
+} bm_index_desc;
+
+/* Validate the descriptor, derive the half-open boxes of every block and
+ * group (a group's box is the smallest box holding its children's boxes) and
+ * copy everything to the current HIP device. *out receives the handle, owned
+ * by the caller until bm_index_destroy. Synchronous.
+ * Errors: BM_EINVAL (null pointer, bad sizes or offsets, ring with fewer than
+ * 3 vertices, parent out of range), BM_ERANGE (coordinate outside
+ * [0, 2^31 - 1]), BM_ENOMEM, BM_EHIP. */
+int bm_index_create(const bm_index_desc* desc, bm_index** out);
+
+/* Free the device copy. Null is accepted. The caller must make sure no work
+ * that uses the index is still queued on any stream. */
+void bm_index_destroy(bm_index* index);
+
+typedef struct {
+  int64_t n_blocks;
+  int64_t n_vertices;      /* as stored on the device (closing copies included) */
+  int64_t n_nodes;         /* groups on all levels plus blocks */
+  int64_t device_bytes;    /* device memory held by the index */
+  int32_t n_levels;        /* group levels */
+  int32_t device;          /* HIP device ordinal holding the index */
+  int64_t top_groups;      /* entities on the coarsest level */
+} bm_index_info;
+
+int bm_index_get_info(const bm_index* index, bm_index_info* info);
+
+/* Save / load the index as a flat binary file (the host-side arrays that
+ * bm_index_create derives), so a large index need not be rebuilt.
+ * bm_index_load places the index on the current device.
+ * Errors: BM_EINVAL, BM_EIO (open/read/write failure or a malformed file),
+ * BM_ENOMEM, BM_EHIP. */
+int bm_index_save(const bm_index* index, const char* path);
+int bm_index_load(const char* path, bm_index** out);
+
+/* ------------------------------------------------------------------------ */
+/* Plain mapping.                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* out_ids[i] = smallest block index whose ring contains point i, or -1.
+ *   xy       device pointer, n interleaved (x, y) int32 points (any values).
+ *   out_ids  device pointer, n int32, written by the call (caller-owned).
+ *   stream   HIP stream the work is queued on (0 = default stream).
+ * Asynchronous: results are ready when the stream reaches this point. The
+ * index must live on the current device. n == 0 is a no-op. xy and out_ids
+ * must not overlap. The index is read-only, so calls on different streams may
+ * run at the same time. Uses no memory beyond its arguments.
+ * Errors: BM_EINVAL (null index, n < 0, null buffers when n > 0, index on
+ * another device), BM_EHIP (launch failure). */
+int map_points(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
+               hipStream_t stream);
+
+/* Longitude/latitude doubles (paper Sec. II) to the int32 fixed point the
+ * index uses: per axis q = rint(v * 2^22) + 2^30 (rint rounds half to even;
+ * the offset is added after rounding, so the result is exact). Resolution
+ * 2^-22 degree. NaN, infinities, |lon| > 180 or |lat| > 90 give (-1, -1),
+ * which lies outside every block of an index built from quantised vertices.
+ *   lonlat  device pointer, n (lon, lat) pairs;  xy  device pointer, n pairs.
+ * Asynchronous on stream. Errors: BM_EINVAL, BM_EHIP. */
+int bm_quantize_lonlat(const double* lonlat, int64_t n, int32_t* xy, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Launch shape. Never changes results, only speed.                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t edge_chunk;       /* ring edges per crossing-test work item: 4, 8 or 16 */
+  int32_t blocks_per_cu;    /* resident workgroups per compute unit (1..8) */
+  int32_t tile_points;      /* points per scheduling tile in the batched form (multiple of 256) */
+} bm_tuning;
+
+/* Fill *t with the defaults used when a tuning pointer is null. */
+int bm_tuning_default(bm_tuning* t);
+
+/* As map_points, with an explicit launch shape (t may be null). */
+int map_points_tuned(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
+                     const bm_tuning* t, hipStream_t stream);
+
+/* Error text for the last failing call on this thread ("" if none). */
+const char* bm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLOCKMAP_H */

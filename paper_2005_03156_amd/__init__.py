@@ -1,0 +1,191 @@
+"""Python binding of libblockmap (argument marshalling only).
+
+Every step of the mapping runs in the HIP kernels of ``libblockmap.so``; this
+module only turns numpy arrays and torch tensors into the pointers, sizes and
+HIP streams of the C interface (``include/blockmap.h``). Torch provides device
+memory and streams. If the library is missing the import fails: there is no
+other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblockmap.so")
+
+BM_OK, BM_EINVAL, BM_ERANGE, BM_ENOMEM, BM_EHIP, BM_EBUSY, BM_ETIMEDOUT, BM_EIO = range(8)
+_NAMES = {0: "BM_OK", 1: "BM_EINVAL", 2: "BM_ERANGE", 3: "BM_ENOMEM", 4: "BM_EHIP", 5: "BM_EBUSY",
+          6: "BM_ETIMEDOUT", 7: "BM_EIO"}
+
+
+class BlockmapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libblockmap.so is not built (run __graft_entry__.build() or "
+                      "python paper_2005_03156_amd/build.py)")
+
+lib = C.CDLL(LIB_PATH)
+
+
+class IndexDesc(C.Structure):
+    _fields_ = [("n_blocks", C.c_int64), ("vert_off", C.c_void_p), ("verts_xy", C.c_void_p),
+                ("n_levels", C.c_int32), ("n_groups", C.c_void_p), ("parent", C.c_void_p)]
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("n_blocks", C.c_int64), ("n_vertices", C.c_int64), ("n_nodes", C.c_int64),
+                ("device_bytes", C.c_int64), ("n_levels", C.c_int32), ("device", C.c_int32),
+                ("top_groups", C.c_int64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("edge_chunk", C.c_int32), ("blocks_per_cu", C.c_int32), ("tile_points", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_P, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32
+_SIGS = {
+    "bm_index_create": (C.c_int, [C.POINTER(IndexDesc), C.POINTER(C.c_void_p)]),
+    "bm_index_destroy": (None, [_P]),
+    "bm_index_get_info": (C.c_int, [_P, C.POINTER(IndexInfo)]),
+    "bm_index_save": (C.c_int, [_P, C.c_char_p]),
+    "bm_index_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_void_p)]),
+    "map_points": (C.c_int, [_P, _P, _I64, _P, _P]),
+    "map_points_tuned": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P]),
+    "bm_quantize_lonlat": (C.c_int, [_P, _I64, _P, _P]),
+    "bm_tuning_default": (C.c_int, [C.POINTER(Tuning)]),
+    "bm_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(rc: int) -> None:
+    if rc != BM_OK:
+        raise BlockmapError(rc, (lib.bm_last_error() or b"").decode())
+
+
+def _stream_handle(stream):
+    """torch stream / raw handle / None -> hipStream_t value."""
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dev_ptr(t, dtype_name: str, shape_tail=()):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError("expected dtype %s, got %s" % (dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError("bad tensor shape %s" % (tuple(t.shape),))
+    return C.c_void_p(t.data_ptr()) if t.numel() else C.c_void_p(0)
+
+
+def tuning_default() -> Tuning:
+    t = Tuning()
+    _check(lib.bm_tuning_default(C.byref(t)))
+    return t
+
+
+class Index:
+    """A block partition and its hierarchy, resident in device memory."""
+
+    def __init__(self, vert_off, verts, n_groups=(), parents=(), *, _handle=None):
+        self._h = None
+        if _handle is not None:
+            self._h = _handle
+            return
+        vo = np.ascontiguousarray(vert_off, np.int64)
+        vv = np.ascontiguousarray(verts, np.int32)
+        ng = np.ascontiguousarray(n_groups, np.int64)
+        pars = [np.ascontiguousarray(p, np.int32) for p in parents]
+        parr = (C.c_void_p * max(len(pars), 1))(*[p.ctypes.data for p in pars])
+        d = IndexDesc(vo.shape[0] - 1, vo.ctypes.data, vv.ctypes.data, len(pars),
+                      ng.ctypes.data if len(pars) else None, C.cast(parr, C.c_void_p))
+        h = C.c_void_p()
+        _check(lib.bm_index_create(C.byref(d), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_geometry(cls, g) -> "Index":
+        return cls(g.vert_off, g.verts, g.n_groups, g.parents)
+
+    @classmethod
+    def load(cls, path: str) -> "Index":
+        h = C.c_void_p()
+        _check(lib.bm_index_load(os.fsencode(path), C.byref(h)))
+        return cls(None, None, _handle=h)
+
+    def save(self, path: str) -> None:
+        _check(lib.bm_index_save(self._h, os.fsencode(path)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = IndexInfo()
+        _check(lib.bm_index_get_info(self._h, C.byref(i)))
+        return {k: int(getattr(i, k)) for k, _ in IndexInfo._fields_}
+
+    def close(self) -> None:
+        h, self._h = self._h, None
+        if h:
+            lib.bm_index_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def map_points(index: Index, xy, out=None, stream=None, tuning: Tuning | None = None):
+    """Block id (or -1) of every point: xy is an int32 CUDA tensor [n, 2]."""
+    import torch
+    n = xy.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=xy.device)
+    pxy = _dev_ptr(xy, "int32", (2,))
+    pout = _dev_ptr(out, "int32")
+    if out.shape[0] != n:
+        raise ValueError("out has the wrong length")
+    s = _stream_handle(stream)
+    if tuning is None:
+        _check(lib.map_points(index.handle, pxy, n, pout, s))
+    else:
+        _check(lib.map_points_tuned(index.handle, pxy, n, pout, C.byref(tuning), s))
+    return out
+
+
+def quantize_lonlat(lonlat, out=None, stream=None):
+    """float64 CUDA tensor [n, 2] of (lon, lat) -> int32 [n, 2] fixed point."""
+    import torch
+    n = lonlat.shape[0]
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int32, device=lonlat.device)
+    _check(lib.bm_quantize_lonlat(_dev_ptr(lonlat, "float64", (2,)), n, _dev_ptr(out, "int32", (2,)),
+                                  _stream_handle(stream)))
+    return out
+
+
+def exported_symbols():
+    return sorted(_SIGS)

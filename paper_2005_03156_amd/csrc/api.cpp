@@ -1,0 +1,159 @@
+// C-ABI entry points of libblockmap: argument checks, error text, launches.
+#include <hip/hip_runtime_api.h>
+
+#include <exception>
+#include <new>
+#include <string>
+
+#include "common.h"
+
+namespace bm {
+
+int index_create(const bm_index_desc* d, bm_index** out);
+void index_destroy(bm_index* ix);
+int index_save(const bm_index* ix, const char* path);
+int index_load(const char* path, bm_index** out);
+
+namespace {
+thread_local std::string g_err;
+}
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* error_text() { return g_err.c_str(); }
+
+Tuning tuning_from(const bm_tuning* t) {
+  Tuning r{8, 2, 1 << 16};
+  if (t) {
+    if (t->edge_chunk == 4 || t->edge_chunk == 8 || t->edge_chunk == 16) r.edge_chunk = t->edge_chunk;
+    if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 8) r.blocks_per_cu = t->blocks_per_cu;
+    if (t->tile_points >= 256 && t->tile_points % 256 == 0) r.tile_points = t->tile_points;
+  }
+  return r;
+}
+
+static int check_device(const bm_index* ix, const char* who) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(BM_EHIP, std::string(who) + ": hipGetDevice: " + hipGetErrorString(e));
+  if (dev != ix->device)
+    return fail(BM_EINVAL, std::string(who) + ": the index lives on device " + std::to_string(ix->device) +
+                               " but device " + std::to_string(dev) + " is current");
+  return BM_OK;
+}
+
+}  // namespace bm
+
+using namespace bm;
+
+#define BM_GUARD(who)                                      \
+  catch (const std::bad_alloc&) {                          \
+    return fail(BM_ENOMEM, std::string(who) + ": out of host memory"); \
+  }                                                        \
+  catch (const std::exception& ex) {                       \
+    return fail(BM_EINVAL, std::string(who) + ": " + ex.what()); \
+  }                                                        \
+  catch (...) {                                            \
+    return fail(BM_EINVAL, std::string(who) + ": unknown error"); \
+  }
+
+extern "C" {
+
+__attribute__((visibility("default"))) int bm_index_create(const bm_index_desc* desc, bm_index** out) {
+  try {
+    clear_error();
+    return index_create(desc, out);
+  }
+  BM_GUARD("bm_index_create")
+}
+
+__attribute__((visibility("default"))) void bm_index_destroy(bm_index* index) {
+  try {
+    index_destroy(index);
+  } catch (...) {
+  }
+}
+
+__attribute__((visibility("default"))) int bm_index_get_info(const bm_index* ix, bm_index_info* info) {
+  if (!ix || !info) return fail(BM_EINVAL, "bm_index_get_info: null argument");
+  info->n_blocks = ix->n_blocks;
+  info->n_vertices = ix->n_verts_stored;
+  info->n_nodes = ix->n_nodes;
+  info->device_bytes = ix->bytes;
+  info->n_levels = ix->k.n_levels;
+  info->device = ix->device;
+  info->top_groups = ix->k.g0;
+  return BM_OK;
+}
+
+__attribute__((visibility("default"))) int bm_index_save(const bm_index* index, const char* path) {
+  try {
+    clear_error();
+    return index_save(index, path);
+  }
+  BM_GUARD("bm_index_save")
+}
+
+__attribute__((visibility("default"))) int bm_index_load(const char* path, bm_index** out) {
+  try {
+    clear_error();
+    return index_load(path, out);
+  }
+  BM_GUARD("bm_index_load")
+}
+
+__attribute__((visibility("default"))) int bm_tuning_default(bm_tuning* t) {
+  if (!t) return fail(BM_EINVAL, "bm_tuning_default: null argument");
+  const Tuning d = tuning_from(nullptr);
+  t->edge_chunk = d.edge_chunk;
+  t->blocks_per_cu = d.blocks_per_cu;
+  t->tile_points = d.tile_points;
+  return BM_OK;
+}
+
+__attribute__((visibility("default"))) int map_points_tuned(const bm_index* index, const int32_t* xy, int64_t n,
+                                                           int32_t* out_ids, const bm_tuning* t,
+                                                           hipStream_t stream) {
+  try {
+    if (!index) return fail(BM_EINVAL, "map_points: null index");
+    if (n < 0) return fail(BM_EINVAL, "map_points: n < 0");
+    if (n == 0) return BM_OK;
+    if (!xy || !out_ids) return fail(BM_EINVAL, "map_points: null buffer");
+    int rc = check_device(index, "map_points");
+    if (rc != BM_OK) return rc;
+    hipError_t e = launch_map(index->k, xy, n, out_ids, tuning_from(t), index->num_cu, stream);
+    if (e != hipSuccess) return fail(BM_EHIP, std::string("map_points: launch: ") + hipGetErrorString(e));
+    return BM_OK;
+  }
+  BM_GUARD("map_points")
+}
+
+__attribute__((visibility("default"))) int map_points(const bm_index* index, const int32_t* xy, int64_t n,
+                                                     int32_t* out_ids, hipStream_t stream) {
+  return map_points_tuned(index, xy, n, out_ids, nullptr, stream);
+}
+
+__attribute__((visibility("default"))) int bm_quantize_lonlat(const double* lonlat, int64_t n, int32_t* xy,
+                                                             hipStream_t stream) {
+  try {
+    if (n < 0) return fail(BM_EINVAL, "bm_quantize_lonlat: n < 0");
+    if (n == 0) return BM_OK;
+    if (!lonlat || !xy) return fail(BM_EINVAL, "bm_quantize_lonlat: null buffer");
+    int dev = 0, cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = launch_quantize(lonlat, n, xy, cu > 0 ? cu : 256, stream);
+    if (e != hipSuccess) return fail(BM_EHIP, std::string("bm_quantize_lonlat: launch: ") + hipGetErrorString(e));
+    return BM_OK;
+  }
+  BM_GUARD("bm_quantize_lonlat")
+}
+
+__attribute__((visibility("default"))) const char* bm_last_error(void) { return error_text(); }
+
+}  // extern "C"

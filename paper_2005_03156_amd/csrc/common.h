@@ -1,0 +1,62 @@
+// Internal declarations shared by the blockmap host code and kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/blockmap.h"
+
+namespace bm {
+
+// Device view of an index. Every entity of every level is a node with a
+// global id: level 0 occupies [0, g0), the next level follows, and the
+// blocks ("leaves") come last, [leaf_base, leaf_base + n_leaves). The
+// children of a group node form one contiguous id range, and consecutive
+// groups own consecutive ranges.
+struct KIndex {
+  const int4* box;           // [n_nodes] half-open (xmin, xmax, ymin, ymax)
+  const int2* child;         // [leaf_base] children of each group node, [begin, end)
+  const int32_t* parent;     // [n_nodes] parent node, -1 on level 0
+  const int64_t* vert_off;   // [n_leaves + 1] ring offsets into verts (leaf order)
+  const int32_t* leaf_id;    // [n_leaves] block index of each leaf as given by the caller
+  const int2* verts;         // rings, each closed by a stored copy of its first vertex
+  int32_t n_levels;          // group levels above the leaves
+  int32_t g0;                // nodes on level 0
+  int32_t leaf_base;         // first leaf node id
+  int32_t n_leaves;
+};
+
+struct Tuning {
+  int edge_chunk;     // 4, 8 or 16
+  int blocks_per_cu;  // 1..8
+  int tile_points;    // batched form scheduling tile
+};
+
+Tuning tuning_from(const bm_tuning* t);
+
+// Launchers (map_kernels.hip). Return hipSuccess or the launch error.
+hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
+                      const Tuning& t, int num_cu, hipStream_t stream);
+hipError_t launch_quantize(const double* lonlat, int64_t n, int32_t* xy, int num_cu,
+                           hipStream_t stream);
+
+// Thread-local error text + code helper.
+int fail(int code, const std::string& msg);
+void clear_error();
+const char* error_text();
+
+}  // namespace bm
+
+struct bm_index {
+  bm::KIndex k;
+  int device;
+  int num_cu;
+  int64_t n_blocks;
+  int64_t n_nodes;
+  int64_t n_verts_stored;
+  int64_t bytes;
+  void* allocs[8];
+  int n_allocs;
+};

@@ -1,0 +1,265 @@
+"""GPU parity: block ids from the HIP kernels equal the CPU oracle's, bit for
+bit, on seeded inputs; plus edge cases and launch-shape invariance."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bm():
+    import paper_2005_03156_amd as bm
+    return bm
+
+
+def gpu_map(bm, torch, ix, pts, tuning=None):
+    xy = torch.from_numpy(np.ascontiguousarray(pts, np.int32)).cuda()
+    out = bm.map_points(ix, xy, tuning=tuning)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def boundary_points(g, k=3000, seed=0):
+    rng = np.random.default_rng(seed)
+    v = g.verts[rng.choice(g.verts.shape[0], min(k, g.verts.shape[0]), replace=False)]
+    offs = np.array([[0, 0], [-1, 0], [0, -1], [1, 0], [0, 1], [-1, -1], [1, 1]], np.int32)
+    return (v[:, None, :] + offs[None]).reshape(-1, 2).astype(np.int32)
+
+
+# ------------------------------------------------------------ config 1 ----
+
+def test_config1_full_vs_brute_force(torch_cuda, bm):
+    say("config1: 100k points + boundary points vs brute force")
+    g = synth.geometry(1)
+    pts = np.concatenate([synth.points(1), boundary_points(g)])
+    ix = bm.Index.from_geometry(g)
+    got = gpu_map(bm, torch_cuda, ix, pts)
+    want = oracle.brute(g.vert_off, g.verts, pts)
+    assert (got == want).all(), int((got != want).sum())
+    assert (want == -1).any() and (want >= 0).any()
+
+
+@pytest.mark.parametrize("chunk", [4, 8, 16])
+@pytest.mark.parametrize("bpc", [1, 3])
+def test_launch_shape_never_changes_results(torch_cuda, bm, chunk, bpc):
+    say("config1 tuning", chunk, bpc)
+    g = synth.geometry(1)
+    pts = np.concatenate([synth.points(1, 30_001), boundary_points(g, 500)])
+    ix = bm.Index.from_geometry(g)
+    t = bm.Tuning(chunk, bpc, 65536)
+    got = gpu_map(bm, torch_cuda, ix, pts, tuning=t)
+    want = oracle.brute(g.vert_off, g.verts, pts)
+    assert (got == want).all()
+
+
+def test_ragged_sizes_and_empty(torch_cuda, bm):
+    g = synth.geometry(1)
+    ix = bm.Index.from_geometry(g)
+    pts = synth.points(1, 5000)
+    want = oracle.brute(g.vert_off, g.verts, pts)
+    for n in [0, 1, 2, 63, 64, 65, 255, 257, 1000, 4999]:
+        say("ragged n =", n)
+        got = gpu_map(bm, torch_cuda, ix, pts[:n])
+        assert got.shape == (n,) and (got == want[:n]).all(), n
+
+
+def test_extreme_coordinates(torch_cuda, bm):
+    say("extreme coordinates")
+    g = synth.geometry(1)
+    ix = bm.Index.from_geometry(g)
+    I32 = np.iinfo(np.int32)
+    vals = [I32.min, I32.min + 1, -1, 0, 1, g.W - 1, g.W, I32.max - 1, I32.max]
+    pts = np.array([[a, b] for a in vals for b in vals], np.int32)
+    got = gpu_map(bm, torch_cuda, ix, pts)
+    assert (got == oracle.brute(g.vert_off, g.verts, pts)).all()
+
+
+# ------------------------------------------------------------ config 2 ----
+
+@pytest.fixture(scope="module")
+def cfg2(bm, torch_cuda):
+    g = synth.geometry(2)
+    return g, bm.Index.from_geometry(g), oracle.Hier.from_geometry(g)
+
+
+def test_config2_two_million_vs_hierarchy_oracle(torch_cuda, bm, cfg2):
+    say("config2: 2M points vs hierarchy oracle; sample vs brute force")
+    g, ix, H = cfg2
+    pts = np.concatenate([synth.points(2, 2_000_000), boundary_points(g, 20_000, seed=3)])
+    got = gpu_map(bm, torch_cuda, ix, pts)
+    want = H.map(pts)
+    assert (got == want).all(), int((got != want).sum())
+    sub = np.random.default_rng(1).choice(pts.shape[0], 1000, replace=False)
+    assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all()
+
+
+def test_config2_full_size_sampled_and_partition_property(torch_cuda, bm, cfg2):
+    """100M points in the benchmark's launch shape: sampled outputs against the
+    oracle, and at every point the partition property (an id exactly when the
+    point lies in [0, W)^2)."""
+    torch = torch_cuda
+    g, ix, H = cfg2
+    n = synth.CONFIGS[2]["n_points"]
+    say("config2 full size: generating", n)
+    pts = synth.points(2, n)
+    xy = torch.from_numpy(pts).cuda()
+    out = bm.map_points(ix, xy)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    say("config2 full size: checking")
+    x, y = pts[:, 0], pts[:, 1]
+    inside = (x >= 0) & (x < g.W) & (y >= 0) & (y < g.W)
+    assert ((got >= 0) == inside).all()
+    assert (got < g.n_blocks).all()
+    sub = np.random.default_rng(7).choice(n, 200_000, replace=False)
+    assert (got[sub] == H.map(pts[sub])).all()
+    # a repeat run gives identical bytes
+    out2 = bm.map_points(ix, xy)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+
+
+# ----------------------------------------------------- hard inputs ----
+
+def _rings_index(bm, rings, n_groups=(), parents=()):
+    off = np.concatenate([[0], np.cumsum([len(r) for r in rings])]).astype(np.int64)
+    verts = np.concatenate([np.asarray(r, np.int32) for r in rings])
+    return off, verts, bm.Index(off, verts, n_groups, parents)
+
+
+def test_nested_squares_overflow_fallback(torch_cuda, bm):
+    """600 nested squares: every point has hundreds of candidates, more than
+    the per-wave lists hold, so the per-point fallback walk decides."""
+    say("nested squares")
+    K = 600
+    rings = [[(0, 0), (10 + k, 0), (10 + k, 10 + k), (0, 10 + k)] for k in range(K)]
+    rng = np.random.default_rng(2)
+    pts = rng.integers(-5, 620, (20000, 2)).astype(np.int32)
+    for L in (0, 1):
+        off, verts, ix = _rings_index(bm, rings, [7] if L else (),
+                                      [np.arange(K, dtype=np.int32) % 7] if L else ())
+        got = gpu_map(bm, torch_cuda, ix, pts)
+        want = oracle.brute(off, verts, pts)
+        assert (got == want).all(), L
+        assert (want > 300).any()
+
+
+def test_heavy_ring_and_many_small(torch_cuda, bm):
+    say("heavy ring")
+    rng = np.random.default_rng(4)
+    m = 20000
+    ang = (np.arange(m) + rng.uniform(0.1, 0.9, m)) * 2 * np.pi / m
+    rad = rng.uniform(4e5, 5e5, m)
+    star = np.stack([1_000_000 + rad * np.cos(ang), 1_000_000 + rad * np.sin(ang)], 1).round().astype(np.int32)
+    tri = [[(10 * i, 0), (10 * i + 9, 0), (10 * i, 9)] for i in range(100)]
+    rings = [star] + tri
+    off, verts, ix = _rings_index(bm, rings)
+    pts = np.concatenate([rng.integers(4e5, 1.6e6, (30000, 2)), rng.integers(-2, 1001, (5000, 2)),
+                          star[:2000], star[:2000] + 1]).astype(np.int32)
+    got = gpu_map(bm, torch_cuda, ix, pts)
+    assert (got == oracle.brute(off, verts, pts)).all()
+
+
+def test_random_hierarchies_and_empty_groups(torch_cuda, bm):
+    g = synth.geometry(1)
+    pts = np.concatenate([synth.points(1, 20000), boundary_points(g, 500)])
+    want = oracle.brute(g.vert_off, g.verts, pts)
+    rng = np.random.default_rng(5)
+    for t in range(3):
+        sizes = sorted(rng.integers(1, 300, 4).tolist())
+        pars = [rng.integers(0, sizes[l], sizes[l + 1]).astype(np.int32) for l in range(3)]
+        pars.append(rng.integers(0, sizes[3], g.n_blocks).astype(np.int32))
+        say("random hierarchy", sizes)
+        ix = bm.Index(g.vert_off, g.verts, sizes, pars)
+        assert (gpu_map(bm, torch_cuda, ix, pts) == want).all()
+    say("flat index")
+    ix = bm.Index(g.vert_off, g.verts)
+    assert (gpu_map(bm, torch_cuda, ix, pts) == want).all()
+
+
+def test_overlapping_blocks_smallest_id(torch_cuda, bm):
+    say("overlaps")
+    rng = np.random.default_rng(6)
+    rings = []
+    for k in range(300):
+        x, y = rng.integers(0, 9000, 2)
+        w, h = rng.integers(50, 2000, 2)
+        rings.append([(x, y), (x + w, y), (x + w, y + h), (x, y + h)])
+    off, verts, ix = _rings_index(bm, rings, [4], [rng.integers(0, 4, 300).astype(np.int32)])
+    pts = rng.integers(-10, 11000, (50000, 2)).astype(np.int32)
+    got = gpu_map(bm, torch_cuda, ix, pts)
+    assert (got == oracle.brute(off, verts, pts)).all()
+
+
+def test_save_load_roundtrip(torch_cuda, bm, tmp_path):
+    say("save/load")
+    g = synth.geometry(1)
+    ix = bm.Index.from_geometry(g)
+    p = str(tmp_path / "cfg1.bmi")
+    ix.save(p)
+    ix2 = bm.Index.load(p)
+    assert ix2.info()["n_blocks"] == g.n_blocks
+    pts = synth.points(1, 10000)
+    assert (gpu_map(bm, torch_cuda, ix2, pts) == gpu_map(bm, torch_cuda, ix, pts)).all()
+    with open(p, "r+b") as f:
+        f.seek(12)
+        f.write(b"\xff\xff\xff\x7f")
+    with pytest.raises(bm.BlockmapError):
+        bm.Index.load(p)
+
+
+# ----------------------------------------------------------- quantiser ----
+
+def test_quantizer_matches_reference(torch_cuda, bm):
+    import json
+    import os
+    from oracle import pyref
+    say("quantiser")
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "quantize_hand.json")))
+    hand = np.array([[float(v) for v in c["lonlat"]] for c in d["cases"]])
+    rng = np.random.default_rng(9)
+    rnd = np.stack([rng.uniform(-181, 181, 100000), rng.uniform(-91, 91, 100000)], 1)
+    ties = (rng.integers(-180 * 2**23, 180 * 2**23, (2000, 2)) / 2**23)  # exact half-steps
+    ties[:, 1] /= 2
+    ll = np.concatenate([hand, rnd, ties])
+    out = bm.quantize_lonlat(torch_cuda.from_numpy(ll).cuda())
+    torch_cuda.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert (got[: len(hand)] == np.array([c["xy"] for c in d["cases"]])).all()
+    assert (got == pyref.quantize_lonlat(ll)).all()
+
+
+def test_quantized_points_map_like_the_oracle(torch_cuda, bm):
+    """Quantiser and mapper chained on the device, against the oracle on the
+    reference quantiser's output."""
+    from oracle import pyref
+    say("quantise + map")
+    g = synth.geometry(1)
+    # a grid of blocks laid over lon/lat: scale config 1 into [2^30, 2^30 + 1e6)
+    off, verts = g.vert_off, (g.verts.astype(np.int64) + 2**30).astype(np.int32)
+    ix = bm.Index(off, verts, g.n_groups, g.parents)
+    rng = np.random.default_rng(10)
+    ll = rng.uniform(-0.01, 0.26, (50000, 2))
+    xy = bm.quantize_lonlat(torch_cuda.from_numpy(ll).cuda())
+    got = bm.map_points(ix, xy).cpu().numpy()
+    want = oracle.brute(off, verts, pyref.quantize_lonlat(ll))
+    assert (got == want).all()
+    assert (want >= 0).any() and (want == -1).any()
