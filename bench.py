@@ -48,6 +48,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--sweep", action="store_true", help="also time every launch shape (stderr)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the mapping path has no multi-GPU form here "
@@ -69,6 +70,18 @@ def main():
     out = torch.empty(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.sweep:
+        for ch in (4, 8, 16):
+            for bpc in (2, 3, 4, 5, 6, 8):
+                t = bm.Tuning(ch, bpc, 65536)
+                bm.map_points(ix, xy, out, stream, tuning=t)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(3):
+                    bm.map_points(ix, xy, out, stream, tuning=t)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                log("sweep chunk=%d blocks/cu=%d: %.3f ms" % (ch, bpc, e0.elapsed_time(e1) / 3))
     for _ in range(args.warmup):
         bm.map_points(ix, xy, out, stream)
     torch.cuda.synchronize()

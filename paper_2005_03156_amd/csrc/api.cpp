@@ -28,7 +28,7 @@ void clear_error() { g_err.clear(); }
 const char* error_text() { return g_err.c_str(); }
 
 Tuning tuning_from(const bm_tuning* t) {
-  Tuning r{8, 2, 1 << 16};
+  Tuning r{8, 6, 1 << 16};
   if (t) {
     if (t->edge_chunk == 4 || t->edge_chunk == 8 || t->edge_chunk == 16) r.edge_chunk = t->edge_chunk;
     if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 8) r.blocks_per_cu = t->blocks_per_cu;

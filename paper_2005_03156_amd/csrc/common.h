@@ -17,7 +17,11 @@ namespace bm {
 // groups own consecutive ranges.
 struct KIndex {
   const int4* box;           // [n_nodes] half-open (xmin, xmax, ymin, ymax)
-  const int2* child;         // [leaf_base] children of each group node, [begin, end)
+  // [leaf_base] per group node: (first child, end of children, offset of the
+  // group's slot table in `slot_mask` or -1, packed table shape: log2 of the
+  // slot count | x shift << 8 | y shift << 16)
+  const int4* child;
+  const unsigned long long* slot_mask;  // per table: S x-slot masks, then S y-slot masks
   const int32_t* parent;     // [n_nodes] parent node, -1 on level 0
   const int64_t* vert_off;   // [n_leaves + 1] ring offsets into verts (leaf order)
   const int32_t* leaf_id;    // [n_leaves] block index of each leaf as given by the caller
@@ -26,6 +30,8 @@ struct KIndex {
   int32_t g0;                // nodes on level 0
   int32_t leaf_base;         // first leaf node id
   int32_t n_leaves;
+  int4 root_child;           // the virtual root: its children are level 0
+  int4 root_box;             // union of the level-0 boxes
 };
 
 struct Tuning {
@@ -56,7 +62,8 @@ struct bm_index {
   int64_t n_blocks;
   int64_t n_nodes;
   int64_t n_verts_stored;
+  int64_t n_masks;
   int64_t bytes;
-  void* allocs[8];
+  void* allocs[12];
   int n_allocs;
 };

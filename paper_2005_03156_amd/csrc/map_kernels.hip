@@ -27,19 +27,19 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kCap = 256;       // (node, point) items per list per wave
-constexpr int kCapChunk = 512;  // crossing-test chunks per window per wave
-constexpr int kL0Lds = 512;     // level-0 boxes staged in LDS when g0 fits
+constexpr int kCapChunk = 256;  // crossing-test chunks per window per wave
+constexpr unsigned kRoot = 0xFFFFFFFFu;
 
 struct WaveLds {
   int2 pts[kWave];
   unsigned best[kWave];
-  unsigned char ovf[kWave];
+  unsigned par[kWave];            // crossing parity of the pairs of one round
   unsigned node[2][kCap];
   unsigned char lane[2][kCap];
-  unsigned parity[kCap];
-  unsigned long long chunk0[kCap];
-  unsigned short ch_pair[kCapChunk];
-  unsigned ch_k[kCapChunk];
+  unsigned char ovf[kWave];
+  unsigned long long ch_j0[kCapChunk];  // first ring vertex of a chunk
+  unsigned char ch_q[kCapChunk];        // pair (within the round) of a chunk
+  unsigned char ch_n[kCapChunk];        // edges in the chunk
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -52,11 +52,7 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return __builtin_amdgcn_readfirstlane(v);
-}
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 __device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v, int lane) {
 #pragma unroll
@@ -126,7 +122,7 @@ __device__ unsigned walk_point(const KIndex& ix, int2 p) {
         if (ring_parity(ix, leaf, p)) best = min(best, (unsigned)ix.leaf_id[leaf]);
         ++e;
       } else {
-        const int2 c = ix.child[e];
+        const int4 c = ix.child[e];
         par = e;
         e = c.x;
         end = c.y;
@@ -157,24 +153,61 @@ __device__ __forceinline__ void emit(WaveLds& S, int dst, bool pred, unsigned no
   cnt += (unsigned)__popcll(m);
 }
 
+// Children of one group per lane (ci = child record, gb = group box, pp =
+// the lane's point): every child whose half-open box holds pp is appended to
+// list `dst`. With a slot table only the children flagged in both the x-slot
+// and the y-slot of pp are tested; otherwise all of them, 64 at a time.
+// Called with all 64 lanes active; `has` masks lanes without an item.
+__device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
+                                       const int4 gb, const int2 pp, int pl, int dst,
+                                       unsigned& cnt) {
+  const int m = has ? ci.y - ci.x : 0;
+  for (int base = 0; wave_any(base < m); base += 64) {
+    unsigned long long cand = 0ull;
+    if (base < m) {
+      const int mm = min(64, m - base);
+      cand = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
+      if (ci.z >= 0) {  // slot table (only groups of at most 64 children have one)
+        const int logS = ci.w & 0xff, shx = (ci.w >> 8) & 0xff, shy = (ci.w >> 16) & 0xff;
+        const long long dx = (long long)pp.x - gb.x, dy = (long long)pp.y - gb.z;
+        const long long sx = dx >> shx, sy = dy >> shy;
+        const long long S_ = 1ll << logS;
+        if (dx < 0 || dy < 0 || sx >= S_ || sy >= S_)
+          cand = 0ull;
+        else
+          cand &= ix.slot_mask[ci.z + sx] & ix.slot_mask[ci.z + S_ + sy];
+      }
+    }
+    const int c0 = ci.x + base;
+    while (wave_any(cand != 0ull)) {
+      const bool h1 = cand != 0ull;
+      const int b1 = h1 ? __builtin_ctzll(cand) : 0;
+      cand &= cand - 1ull;
+      const bool h2 = cand != 0ull;
+      const int b2 = h2 ? __builtin_ctzll(cand) : 0;
+      cand &= cand - 1ull;
+      int4 bx1 = make_int4(0, 0, 0, 0), bx2 = make_int4(0, 0, 0, 0);
+      if (h1) bx1 = ix.box[c0 + b1];
+      if (h2) bx2 = ix.box[c0 + b2];
+      emit(S, dst, h1 && in_box(bx1, pp), (unsigned)(c0 + b1), pl, cnt);
+      emit(S, dst, h2 && in_box(bx2, pp), (unsigned)(c0 + b2), pl, cnt);
+    }
+  }
+}
+
 template <int kChunkShift>
 __global__ __launch_bounds__(kBlock) void map_kernel(const KIndex ix, const int2* __restrict__ xy,
                                                      const long long n, int* __restrict__ out) {
-  constexpr unsigned kChunk = 1u << kChunkShift;
-  __shared__ int4 l0box[kL0Lds];
+  constexpr int kChunk = 1 << kChunkShift;
   __shared__ WaveLds wl[kWavesPerBlock];
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  WaveLds& S = wl[w];
-  const bool l0_lds = ix.g0 <= kL0Lds;
-  if (l0_lds)
-    for (int i = threadIdx.x; i < ix.g0; i += kBlock) l0box[i] = ix.box[i];
-  __syncthreads();
+  WaveLds& S = wl[threadIdx.x / kWave];
 
   const long long ntiles = (n + kWave - 1) / kWave;
   const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
-  for (long long t = (long long)blockIdx.x * kWavesPerBlock + w; t < ntiles; t += nwaves) {
+  for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
+       t += nwaves) {
     const long long i = t * kWave + lane;
     const bool valid = i < n;
     const int2 p = valid ? xy[i] : make_int2(0, 0);
@@ -183,13 +216,10 @@ __global__ __launch_bounds__(kBlock) void map_kernel(const KIndex ix, const int2
     S.ovf[lane] = 0;
     wave_sync();
 
-    // ---- level 0: every point against every level-0 box (uniform loop)
+    // ---- the root's children (level 0), one item per point
     int cur = 0;
     unsigned cnt = 0;
-    for (int j = 0; j < ix.g0; ++j) {
-      const int4 b = l0_lds ? l0box[j] : ix.box[j];
-      emit(S, cur, valid && in_box(b, p), (unsigned)j, lane, cnt);
-    }
+    expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt);
     cnt = min(cnt, (unsigned)kCap);
     wave_sync();
 
@@ -202,88 +232,65 @@ __global__ __launch_bounds__(kBlock) void map_kernel(const KIndex ix, const int2
         const bool has = q < cnt;
         const unsigned node = has ? S.node[cur][q] : 0u;
         const int pl = has ? S.lane[cur][q] : 0;
-        const int2 cr = has ? ix.child[node] : make_int2(0, 0);
-        const int2 pp = S.pts[pl];
-        const int len = cr.y - cr.x;
-        const int maxlen = wave_max(len);
-        for (int k = 0; k < maxlen; ++k) {
-          const bool act = k < len;
-          const int c = cr.x + (act ? k : 0);
-          const bool in = act && in_box(ix.box[act ? c : 0], pp);
-          emit(S, nxt, in, (unsigned)c, pl, ncnt);
+        int4 ci = make_int4(0, 0, -1, 0), gb = make_int4(0, 0, 0, 0);
+        if (has) {
+          ci = ix.child[node];
+          gb = ix.box[node];
         }
+        expand(ix, S, has, ci, gb, S.pts[pl], pl, nxt, ncnt);
       }
       cnt = min(ncnt, (unsigned)kCap);
       cur = nxt;
       wave_sync();
     }
 
-    // ---- crossing-number test on the (leaf, point) pairs in list `cur`
-    unsigned long long total = 0;
+    // ---- crossing-number test on the (leaf, point) pairs of list `cur`,
+    // 64 pairs per round; each pair's ring edges are cut into chunks of
+    // kChunk edges and all chunks of the round are dealt across the lanes.
     for (unsigned r = 0; r < cnt; r += kWave) {
       const unsigned q = r + lane;
       const bool has = q < cnt;
-      unsigned long long nch = 0;
+      long long v0 = 0, v1 = 0;
+      unsigned bid = 0;
       if (has) {
         const int leaf = (int)S.node[cur][q] - ix.leaf_base;
-        const long long edges = ix.vert_off[leaf + 1] - ix.vert_off[leaf] - 1;
-        nch = (unsigned long long)((edges + kChunk - 1) >> kChunkShift);
+        v0 = ix.vert_off[leaf];
+        v1 = ix.vert_off[leaf + 1] - 1;  // index of the closing copy
+        bid = (unsigned)ix.leaf_id[leaf];
       }
+      const unsigned long long nch = has ? (unsigned long long)((v1 - v0 + kChunk - 1) >> kChunkShift) : 0ull;
       const unsigned long long incl = wave_incl_scan(nch, lane);
-      if (has) {
-        S.chunk0[q] = total + incl - nch;
-        S.parity[q] = 0;
-      }
-      total += __shfl(incl, kWave - 1);
-    }
-    wave_sync();
-
-    for (unsigned long long wlo = 0; wlo < total; wlo += kCapChunk) {
-      const unsigned long long whi = min(wlo + (unsigned long long)kCapChunk, total);
-      // deal this window's chunks: pair q owns chunk ids [chunk0[q], chunk0[q+1])
-      for (unsigned r = 0; r < cnt; r += kWave) {
-        const unsigned q = r + lane;
-        if (q < cnt) {
-          const unsigned long long c0 = S.chunk0[q];
-          const unsigned long long c1 = (q + 1 < cnt) ? S.chunk0[q + 1] : total;
-          const unsigned long long a = max(c0, wlo), b = min(c1, whi);
-          for (unsigned long long c = a; c < b; ++c) {
-            S.ch_pair[c - wlo] = (unsigned short)q;
-            S.ch_k[c - wlo] = (unsigned)(c - c0);
-          }
+      const unsigned long long start = incl - nch;
+      const unsigned long long total = __shfl(incl, kWave - 1);
+      S.par[lane] = 0;
+      for (unsigned long long w = 0; w < total; w += kCapChunk) {
+        const unsigned long long a = max(start, w), b = min(start + nch, w + (unsigned long long)kCapChunk);
+        for (unsigned long long c = a; c < b; ++c) {
+          const long long j0 = v0 + (long long)((c - start) << kChunkShift);
+          S.ch_j0[c - w] = (unsigned long long)j0;
+          S.ch_q[c - w] = (unsigned char)lane;
+          S.ch_n[c - w] = (unsigned char)min((long long)kChunk, v1 - j0);
         }
-      }
-      wave_sync();
-      const unsigned nwin = (unsigned)(whi - wlo);
-      for (unsigned c = lane; c < nwin; c += kWave) {
-        const unsigned q = S.ch_pair[c];
-        const unsigned k = S.ch_k[c];
-        const int leaf = (int)S.node[cur][q] - ix.leaf_base;
-        const int2 pp = S.pts[S.lane[cur][q]];
-        const long long v0 = ix.vert_off[leaf];
-        const long long vlast = ix.vert_off[leaf + 1] - 1;  // index of the closing copy
-        const long long j0 = v0 + ((long long)k << kChunkShift);
-        const long long j1 = min(j0 + (long long)kChunk, vlast);
-        int2 a = ix.verts[j0];
-        unsigned acc = 0;
-        for (long long j = j0; j < j1; ++j) {
-          const int2 b = ix.verts[j + 1];
-          acc ^= crosses(a, b, pp);
-          a = b;
+        wave_sync();
+        const unsigned nw = (unsigned)min((unsigned long long)kCapChunk, total - w);
+        for (unsigned c = lane; c < nw; c += kWave) {
+          const long long j0 = (long long)S.ch_j0[c];
+          const int ne = S.ch_n[c];
+          const unsigned pq = S.ch_q[c];
+          int2 v[kChunk + 1];
+#pragma unroll
+          for (int u = 0; u <= kChunk; ++u) v[u] = (u <= ne) ? ix.verts[j0 + u] : make_int2(0, 0);
+          const int2 pp = S.pts[S.lane[cur][r + pq]];
+          unsigned acc = 0;
+#pragma unroll
+          for (int u = 0; u < kChunk; ++u) acc ^= (u < ne) ? crosses(v[u], v[u + 1], pp) : 0u;
+          if (acc) atomicXor(&S.par[pq], 1u);
         }
-        if (acc) atomicXor(&S.parity[q], 1u);
+        wave_sync();
       }
+      if (has && (S.par[lane] & 1u)) atomicMin(&S.best[S.lane[cur][q]], bid);
       wave_sync();
     }
-
-    for (unsigned r = 0; r < cnt; r += kWave) {
-      const unsigned q = r + lane;
-      if (q < cnt && (S.parity[q] & 1u)) {
-        const int leaf = (int)S.node[cur][q] - ix.leaf_base;
-        atomicMin(&S.best[S.lane[cur][q]], (unsigned)ix.leaf_id[leaf]);
-      }
-    }
-    wave_sync();
 
     unsigned best = S.best[lane];
     if (valid && S.ovf[lane]) best = min(best, walk_point(ix, p));
