@@ -62,6 +62,12 @@ def _L():
         lib.syn_mixture_points.argtypes = [u64, i64, i64, i32, P, P, P, P, dbl, dbl, dbl, P]
         lib.syn_sizes.restype = None
         lib.syn_sizes.argtypes = [u64, i64, i32, dbl, dbl, dbl, P]
+        lib.syn_qt_offsets.restype = i64
+        lib.syn_qt_offsets.argtypes = [P, i64, P]
+        lib.syn_qt_fill.restype = None
+        lib.syn_qt_fill.argtypes = [P, i64, P, P]
+        lib.syn_qt_groups.restype = i64
+        lib.syn_qt_groups.argtypes = [P, i64, P, P]
         _lib = lib
     return _lib
 
@@ -142,6 +148,8 @@ CONFIGS = {
 
 
 def geometry(cfg: int) -> Geometry:
+    if cfg == 3:
+        return quadtree_geometry(**QUADTREE)
     p = CONFIGS[cfg]
     off, verts = jittered_grid(p["n"], p["c"], klaw=p["klaw"], kmin=p["kmin"], kmax=p["kmax"],
                                kp=p["kp"], key_=key(cfg, 0, 0))
@@ -171,6 +179,10 @@ class Mixture:
 
 def points(cfg: int, n: int | None = None, i0: int = 0, out: np.ndarray | None = None) -> np.ndarray:
     """Points i0 .. i0+n-1 of a config's point stream (int32 [n, 2])."""
+    if cfg == 3:
+        q = QUADTREE
+        n = q["n_points"] if n is None else n
+        return quadtree_mixture(q).sample(key(3, 1, 1), i0, n, out)
     p = CONFIGS[cfg]
     W = p["n"] * p["c"]
     n = p["n_points"] if n is None else n
@@ -182,3 +194,99 @@ def sizes(key_: int, nb: int, law: int, median: float, s: float, hi: float) -> n
     out = np.empty(nb, np.int64)
     _L().syn_sizes(key_, nb, law, median, s, hi, _p(out))
     return out
+
+
+# ------------------------------------------------ graded quadtree mesh ----
+
+class _QtParams(C.Structure):
+    _fields_ = [("R", C.c_int32), ("lg_cell", C.c_int32), ("maxd", C.c_int32), ("depth", C.c_void_p),
+                ("leaf_off", C.c_void_p), ("vjit", C.c_double), ("pjit", C.c_double),
+                ("taper", C.c_double), ("k_lambda", C.c_double), ("k_alpha", C.c_double),
+                ("vmax", C.c_int32), ("key", C.c_uint64), ("factor", C.c_void_p)]
+
+
+# config 3: 2^30 square of 512 x 512 root cells, each cut into 4^d equal
+# leaves (d <= 5, neighbours differ by <= 1) following the point density, to
+# about 8M leaves; per-segment interior points from a Lomax(2) law (block
+# mean about 30, 4..2000 vertices); hierarchy 64 / 4,096 / 262,144 root cells
+# / depth-2 quadtree nodes / leaves; 1B points in chunks of 2^26.
+QUADTREE = dict(R=512, lg_cell=21, maxd=5, target_leaves=8_000_000, vjit=0.25, pjit=0.10, taper=0.2,
+                k_lambda=7.0, k_alpha=2.0, vmax=2000, K=64, wsig=1.0, sig=(0.002, 0.03), p_unif=0.03,
+                n_points=1_000_000_000, chunk=1 << 26, cfg=3)
+
+
+def quadtree_mixture(q) -> Mixture:
+    W = float(q["R"] << q["lg_cell"])
+    return Mixture(key(q["cfg"], 1, 0), q["K"], W, q["wsig"], q["sig"][0], q["sig"][1], q["p_unif"])
+
+
+def _balance(d: np.ndarray) -> np.ndarray:
+    """Raise depths until 8-neighbours differ by at most one."""
+    d = d.copy()
+    while True:
+        p = np.pad(d, 1, constant_values=-1)
+        m = np.max(np.stack([p[1 + a:p.shape[0] - 1 + a, 1 + b:p.shape[1] - 1 + b]
+                             for a in (-1, 0, 1) for b in (-1, 0, 1)]), 0)
+        nd = np.maximum(d, m - 1)
+        if (nd == d).all():
+            return d
+        d = nd
+
+
+def quadtree_depths(q) -> np.ndarray:
+    """Depth per root cell from the expected point count of the density the
+    points are drawn from: deeper where points are denser."""
+    from scipy.special import ndtr
+    R, cell = q["R"], float(1 << q["lg_cell"])
+    W = R * cell
+    mix = quadtree_mixture(q)
+    w = np.diff(np.concatenate([[0.0], mix.cumw]))
+    edges = np.arange(R + 1) * cell
+    px = ndtr((edges[None, :] - mix.cx[:, None]) / mix.sig[:, None])
+    py = ndtr((edges[None, :] - mix.cy[:, None]) / mix.sig[:, None])
+    px, py = np.diff(px, axis=1), np.diff(py, axis=1)  # [K, R]
+    prob = (1 - q["p_unif"]) * np.einsum("k,ki,kj->ji", w, px, py)
+    prob += q["p_unif"] * (cell * cell) / (1.1 * W) ** 2
+    E = prob * q["n_points"]
+
+    def depths(T):
+        d = np.clip(np.ceil(np.log(np.maximum(E / T, 1e-30)) / np.log(4.0)), 0, q["maxd"]).astype(np.int8)
+        return _balance(d)
+
+    lo, hi = np.log(1e-3), np.log(1e12)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        n = int((4 ** depths(np.exp(mid)).astype(np.int64)).sum())
+        if n > q["target_leaves"]:
+            lo = mid
+        else:
+            hi = mid
+    return depths(np.exp(hi))
+
+
+def quadtree_geometry(**q) -> Geometry:
+    R = q["R"]
+    depth = np.ascontiguousarray(quadtree_depths(q), np.int8).ravel()
+    leaf_off = np.concatenate([[0], np.cumsum(4 ** depth.astype(np.int64))]).astype(np.int64)
+    nl = int(leaf_off[-1])
+    factor = np.empty(nl, np.float32)
+    qp = _QtParams(R, q["lg_cell"], q["maxd"], depth.ctypes.data, leaf_off.ctypes.data, q["vjit"],
+                   q["pjit"], q["taper"], q["k_lambda"], q["k_alpha"], q["vmax"], key(q["cfg"], 0, 0),
+                   factor.ctypes.data)
+    off = np.empty(nl + 1, np.int64)
+    total = _L().syn_qt_offsets(C.byref(qp), nl, _p(off))
+    verts = np.empty((total, 2), np.int32)
+    _L().syn_qt_fill(C.byref(qp), nl, _p(off), _p(verts))
+    # hierarchy: 64 tiles / 4096 tiles / root cells / depth-2 quadtree nodes / leaves
+    leaf_group = np.empty(nl, np.int32)
+    group_cell = np.empty(nl, np.int32)
+    ng = int(_L().syn_qt_groups(C.byref(qp), nl, _p(leaf_group), _p(group_cell)))
+    group_cell = group_cell[:ng].copy()
+    cy, cx = np.divmod(np.arange(R * R), R)
+    t1 = (cy // 8) * (R // 8) + cx // 8
+    ty, tx = np.divmod(np.arange((R // 8) ** 2), R // 8)
+    t0 = (ty // 8) * (R // 64) + tx // 8
+    parents = [t0.astype(np.int32), t1.astype(np.int32), group_cell, leaf_group]
+    n_groups = [(R // 64) ** 2, (R // 8) ** 2, R * R, ng]
+    return Geometry(off, verts, n_groups, parents, W=R << q["lg_cell"], name="config3",
+                    meta=dict(depth=depth.reshape(R, R), leaf_off=leaf_off))

@@ -288,3 +288,260 @@ SYN_API void syn_sizes(uint64_t key, int64_t nb, int32_t law, double median, dou
     out[b] = (int64_t)v;
   }
 }
+
+/* ------------------------------------------- graded quadtree mesh ---- */
+/*
+ * A square of R x R root cells, each of side 2^lg_cell units. Root cell c is
+ * cut into a 2^d x 2^d grid of equal leaves, d = depth[c] in [0, maxd];
+ * neighbouring root cells (8-neighbourhood) differ in depth by at most one,
+ * so a leaf side meets at most two leaves of the other side. All leaf corners
+ * lie on a lattice of step 2^(lg_cell - maxd) ("lattice units"). A leaf side
+ * whose neighbour is one level finer carries the neighbour's corner at its
+ * midpoint (a T-junction) so the rings stay watertight.
+ *
+ * Shared features are derived from lattice coordinates alone, so both sides of
+ * a boundary generate them identically and independently:
+ *   - lattice vertex (X, Y): jittered by +-vjit of the smallest adjacent leaf
+ *     (hull vertices only along the hull, hull corners fixed);
+ *   - segment between two consecutive boundary vertices: k interior points,
+ *     k from a Lomax (Pareto II) law, perpendicular offset +-pjit of the
+ *     segment length tapered to taper * distance to the nearer end (no offset
+ *     on the hull). Blocks over vmax vertices have their segments' k scaled
+ *     down (a shared segment takes the smaller of its two blocks' factors).
+ * Leaves are numbered by root cell (row-major), then row-major inside it.
+ */
+typedef struct {
+  int32_t R, lg_cell, maxd;
+  const int8_t* depth;      /* [R*R] */
+  const int64_t* leaf_off;  /* [R*R+1] leaves before each root cell */
+  double vjit, pjit, taper;
+  double k_lambda, k_alpha; /* Lomax scale and shape */
+  int32_t vmax;             /* vertex cap per block */
+  uint64_t key;
+  float* factor;            /* [n_leaves] k scale per block (filled by syn_qt_offsets) */
+} syn_qt;
+
+static inline int qt_depth_at(const syn_qt* q, int64_t cx, int64_t cy) {
+  if (cx < 0 || cy < 0 || cx >= q->R || cy >= q->R) return -1;
+  return q->depth[cy * q->R + cx];
+}
+
+/* depth of the leaf containing lattice cell (X, Y) (lower-left corner lattice
+ * coordinate of a finest cell), -1 outside */
+static inline int qt_depth_cell(const syn_qt* q, int64_t X, int64_t Y) {
+  const int64_t per = (int64_t)1 << q->maxd;
+  if (X < 0 || Y < 0) return -1;
+  return qt_depth_at(q, X / per, Y / per);
+}
+
+/* leaf id of the leaf containing finest lattice cell (X, Y) */
+static inline int64_t qt_leaf_at(const syn_qt* q, int64_t X, int64_t Y) {
+  const int64_t per = (int64_t)1 << q->maxd;
+  if (X < 0 || Y < 0 || X >= per * q->R || Y >= per * q->R) return -1;
+  const int64_t cx = X / per, cy = Y / per, c = cy * q->R + cx;
+  const int d = q->depth[c];
+  const int64_t L = per >> d;
+  const int64_t i = (X - cx * per) / L, j = (Y - cy * per) / L;
+  return q->leaf_off[c] + j * ((int64_t)1 << d) + i;
+}
+
+static void qt_vertex(const syn_qt* q, int64_t X, int64_t Y, double* x, double* y) {
+  const int64_t per = (int64_t)1 << q->maxd, N = per * q->R;
+  const double unit = (double)((int64_t)1 << (q->lg_cell - q->maxd));
+  int dmax = -1;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      int d = qt_depth_cell(q, X - a, Y - b);
+      if (d > dmax) dmax = d;
+    }
+  const double s = unit * (double)(per >> (dmax < 0 ? 0 : dmax));
+  const uint64_t kv = mix64(q->key ^ 0x7E47ull);
+  const uint64_t id = (uint64_t)Y * (uint64_t)(N + 1) + (uint64_t)X;
+  double px = (double)X * unit, py = (double)Y * unit;
+  if (X != 0 && X != N) px += (2.0 * u01(kv, 2 * id) - 1.0) * q->vjit * s;
+  if (Y != 0 && Y != N) py += (2.0 * u01(kv, 2 * id + 1) - 1.0) * q->vjit * s;
+  *x = rint(px);
+  *y = rint(py);
+}
+
+/* raw interior point count of the segment between lattice vertices A < B */
+static inline int32_t qt_seg_k_raw(const syn_qt* q, uint64_t sid) {
+  const double u = u01(mix64(q->key ^ 0x6B5Aull), sid);
+  double k = floor(q->k_lambda * (pow(1.0 - u, -1.0 / q->k_alpha) - 1.0));
+  if (k > (double)q->vmax) k = (double)q->vmax;
+  return (int32_t)k;
+}
+
+/* segment id from its two lattice endpoints (order independent) */
+static inline uint64_t qt_seg_id(const syn_qt* q, int64_t X0, int64_t Y0, int64_t X1, int64_t Y1) {
+  const int64_t N = ((int64_t)1 << q->maxd) * q->R + 1;
+  uint64_t a = (uint64_t)(Y0 * N + X0), b = (uint64_t)(Y1 * N + X1);
+  if (a > b) { uint64_t t = a; a = b; b = t; }
+  return mix64(a) ^ (b * 0x9E3779B97F4A7C15ull);
+}
+
+/* The boundary of leaf (corner (X0,Y0), side L lattice units) as up to 8
+ * lattice vertices, counter-clockwise from the lower-left corner. */
+static int qt_ring_corners(const syn_qt* q, int64_t X0, int64_t Y0, int64_t L, int d,
+                           int64_t* vx, int64_t* vy) {
+  int n = 0;
+  const int64_t cx[4] = {X0, X0 + L, X0 + L, X0};
+  const int64_t cy[4] = {Y0, Y0, Y0 + L, Y0 + L};
+  /* finest cell just across the middle of each side: below, right, above, left */
+  const int64_t h = L / 2;
+  const int64_t ox[4] = {X0 + h, X0 + L, X0 + h, X0 - 1};
+  const int64_t oy[4] = {Y0 - 1, Y0 + h, Y0 + L, Y0 + h};
+  for (int s = 0; s < 4; ++s) {
+    vx[n] = cx[s]; vy[n] = cy[s]; ++n;
+    if (L >= 2 && qt_depth_cell(q, ox[s], oy[s]) > d) {
+      vx[n] = (cx[s] + cx[(s + 1) & 3]) / 2;
+      vy[n] = (cy[s] + cy[(s + 1) & 3]) / 2;
+      ++n;
+    }
+  }
+  return n;
+}
+
+static void qt_leaf_geom(const syn_qt* q, int64_t leaf, int64_t* X0, int64_t* Y0, int64_t* L, int* d) {
+  /* root cell by binary search on leaf_off */
+  int64_t lo = 0, hi = (int64_t)q->R * q->R - 1;
+  while (lo < hi) {
+    int64_t m = (lo + hi + 1) / 2;
+    if (q->leaf_off[m] <= leaf) lo = m; else hi = m - 1;
+  }
+  const int64_t c = lo, per = (int64_t)1 << q->maxd;
+  *d = q->depth[c];
+  *L = per >> *d;
+  const int64_t r = leaf - q->leaf_off[c], side = (int64_t)1 << *d;
+  *X0 = (c % q->R) * per + (r % side) * *L;
+  *Y0 = (c / q->R) * per + (r / side) * *L;
+}
+
+/* The leaf across the segment A -> B, which its own leaf walks counter-
+ * clockwise (interior on the left): take the finest lattice cell just to the
+ * right of the segment; -1 beyond the hull. */
+static int64_t qt_other_leaf(const syn_qt* q, int64_t ax, int64_t ay, int64_t bx, int64_t by) {
+  int64_t X, Y;
+  if (ay == by) {
+    X = ax < bx ? ax : bx;
+    Y = bx > ax ? ay - 1 : ay;
+  } else {
+    Y = ay < by ? ay : by;
+    X = by > ay ? ax : ax - 1;
+  }
+  return qt_leaf_at(q, X, Y);
+}
+
+static int32_t qt_seg_k(const syn_qt* q, int64_t self, int64_t ax, int64_t ay, int64_t bx, int64_t by) {
+  const int32_t raw = qt_seg_k_raw(q, qt_seg_id(q, ax, ay, bx, by));
+  float f = q->factor ? q->factor[self] : 1.0f;
+  if (q->factor) {
+    int64_t o = qt_other_leaf(q, ax, ay, bx, by);
+    if (o >= 0 && q->factor[o] < f) f = q->factor[o];
+  }
+  if (f >= 1.0f) return raw;
+  return (int32_t)floor((double)raw * (double)f);
+}
+
+/* Offsets of every ring (no closing duplicate); also fills q->factor. */
+SYN_API int64_t syn_qt_offsets(syn_qt* q, int64_t n_leaves, int64_t* vert_off) {
+  float* fac = q->factor;
+  q->factor = NULL;
+  /* pass 1: raw totals -> scale factors */
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t leaf = 0; leaf < n_leaves; ++leaf) {
+    int64_t X0, Y0, L, vx[8], vy[8];
+    int d;
+    qt_leaf_geom(q, leaf, &X0, &Y0, &L, &d);
+    const int nc = qt_ring_corners(q, X0, Y0, L, d, vx, vy);
+    int64_t tot = nc, ks = 0;
+    for (int s = 0; s < nc; ++s) ks += qt_seg_k_raw(q, qt_seg_id(q, vx[s], vy[s], vx[(s + 1) % nc], vy[(s + 1) % nc]));
+    tot += ks;
+    fac[leaf] = (tot > q->vmax && ks > 0) ? (float)((double)(q->vmax - nc) / (double)ks) : 1.0f;
+  }
+  q->factor = fac;
+  /* pass 2: final counts */
+  vert_off[0] = 0;
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t leaf = 0; leaf < n_leaves; ++leaf) {
+    int64_t X0, Y0, L, vx[8], vy[8];
+    int d;
+    qt_leaf_geom(q, leaf, &X0, &Y0, &L, &d);
+    const int nc = qt_ring_corners(q, X0, Y0, L, d, vx, vy);
+    int64_t tot = nc;
+    for (int s = 0; s < nc; ++s) tot += qt_seg_k(q, leaf, vx[s], vy[s], vx[(s + 1) % nc], vy[(s + 1) % nc]);
+    vert_off[leaf + 1] = tot;
+  }
+  for (int64_t leaf = 0; leaf < n_leaves; ++leaf) vert_off[leaf + 1] += vert_off[leaf];
+  return vert_off[n_leaves];
+}
+
+SYN_API void syn_qt_fill(const syn_qt* q, int64_t n_leaves, const int64_t* vert_off, int32_t* verts) {
+#pragma omp parallel
+  {
+    int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(q->vmax + 8));
+#pragma omp for schedule(dynamic, 4096)
+    for (int64_t leaf = 0; leaf < n_leaves; ++leaf) {
+      int64_t X0, Y0, L, vx[8], vy[8];
+      int d;
+      qt_leaf_geom(q, leaf, &X0, &Y0, &L, &d);
+      const int nc = qt_ring_corners(q, X0, Y0, L, d, vx, vy);
+      const int64_t per = (int64_t)1 << q->maxd, N = per * q->R;
+      int32_t* o = verts + 2 * vert_off[leaf];
+      for (int s = 0; s < nc; ++s) {
+        const int64_t ax = vx[s], ay = vy[s], bx = vx[(s + 1) % nc], by = vy[(s + 1) % nc];
+        double fx, fy, gx, gy;
+        qt_vertex(q, ax, ay, &fx, &fy);
+        *o++ = (int32_t)fx;
+        *o++ = (int32_t)fy;
+        const int32_t k = qt_seg_k(q, leaf, ax, ay, bx, by);
+        if (k == 0) continue;
+        /* generate in canonical direction (smaller lattice id first) */
+        const int rev = (ay * (N + 1) + ax) > (by * (N + 1) + bx);
+        const int64_t cax = rev ? bx : ax, cay = rev ? by : ay, cbx = rev ? ax : bx, cby = rev ? ay : by;
+        double px0, py0, px1, py1;
+        qt_vertex(q, cax, cay, &px0, &py0);
+        qt_vertex(q, cbx, cby, &px1, &py1);
+        const int hull = (cax == cbx && (cax == 0 || cax == N)) || (cay == cby && (cay == 0 || cay == N));
+        const uint64_t ko = mix64(mix64(q->key ^ 0x0FF5ull) + qt_seg_id(q, cax, cay, cbx, cby));
+        const double dx = px1 - px0, dy = py1 - py0, Ls = sqrt(dx * dx + dy * dy);
+        for (int32_t m = 1; m <= k; ++m) {
+          const double t = (double)m / (double)(k + 1);
+          double off = 0.0;
+          if (!hull) {
+            off = (2.0 * u01(ko, (uint64_t)m) - 1.0) * q->pjit * Ls;
+            const double lim = q->taper * (t < 1.0 - t ? t : 1.0 - t) * Ls;
+            off = clampd(off, -lim, lim);
+          }
+          tmp[2 * (m - 1)] = to_i32(px0 + t * dx - off * dy / Ls);
+          tmp[2 * (m - 1) + 1] = to_i32(py0 + t * dy + off * dx / Ls);
+        }
+        if (rev) put_reversed(o, tmp, k);
+        else memcpy(o, tmp, sizeof(int32_t) * 2 * (size_t)k);
+        o += 2 * k;
+      }
+    }
+    free(tmp);
+  }
+}
+
+/* leaf -> (root cell, quadtree node at depth min(d, 2) inside it) for the
+ * hierarchy; writes per leaf the index of its depth-2 group and per group its
+ * root cell. Returns the number of groups. */
+SYN_API int64_t syn_qt_groups(const syn_qt* q, int64_t n_leaves, int32_t* leaf_group, int32_t* group_cell) {
+  int64_t ng = 0;
+  const int64_t C = (int64_t)q->R * q->R;
+  for (int64_t c = 0; c < C; ++c) {
+    const int d = q->depth[c];
+    const int dg = d < 2 ? d : 2;
+    const int64_t side = (int64_t)1 << d, gside = (int64_t)1 << dg, sh = d - dg;
+    for (int64_t r = 0; r < side * side; ++r) {
+      const int64_t i = r % side, j = r / side;
+      leaf_group[q->leaf_off[c] + r] = (int32_t)(ng + (j >> sh) * gside + (i >> sh));
+    }
+    for (int64_t g = 0; g < gside * gside; ++g) group_cell[ng + g] = (int32_t)c;
+    ng += gside * gside;
+  }
+  (void)n_leaves;
+  return ng;
+}

@@ -263,3 +263,34 @@ def test_quantized_points_map_like_the_oracle(torch_cuda, bm):
     want = oracle.brute(off, verts, pyref.quantize_lonlat(ll))
     assert (got == want).all()
     assert (want >= 0).any() and (want == -1).any()
+
+
+# ------------------------------------------------------------ config 3 ----
+
+def test_config3_streamed_billion_points(torch_cuda, bm):
+    """8M-block graded mesh, 1B points in 2^26-point chunks: every output obeys
+    the partition property, a full 8M slice equals the hierarchy oracle, and
+    sampled points equal brute force."""
+    torch = torch_cuda
+    say("config3: generating geometry")
+    g = synth.geometry(3)
+    ix = bm.Index.from_geometry(g)
+    H = oracle.Hier.from_geometry(g)
+    q = synth.QUADTREE
+    N, CH = q["n_points"], q["chunk"]
+    rng = np.random.default_rng(12)
+    out = torch.empty(CH, dtype=torch.int32, device="cuda")
+    for k in range((N + CH - 1) // CH):
+        n = min(CH, N - k * CH)
+        pts = synth.points(3, n, i0=k * CH)
+        xy = torch.from_numpy(pts).cuda()
+        bm.map_points(ix, xy, out[:n])
+        got = out[:n].cpu().numpy()
+        x, y = pts[:, 0], pts[:, 1]
+        inside = (x >= 0) & (x < g.W) & (y >= 0) & (y < g.W)
+        assert ((got >= 0) == inside).all(), k
+        sub = rng.choice(n, 300, replace=False)
+        assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all(), k
+        if k == 0:
+            assert (got[:8_000_000] == H.map(pts[:8_000_000])).all()
+        say("config3 chunk", k, "ok", n)
