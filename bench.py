@@ -49,6 +49,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--sweep", action="store_true", help="also time every launch shape (stderr)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--config3", action="store_true",
                     help="also measure the 8M-block graded mesh streamed over 1B points (stderr)")
     args = ap.parse_args()
@@ -127,11 +128,97 @@ def main():
         "hbm": {"achieved_GBs": hbm_gbs, "peak_GBs": PEAK_HBM_GBS, "frac": hbm_gbs / PEAK_HBM_GBS,
                 "bytes_per_point": BYTES_PER_POINT},
     }
+    del xy, out
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        res["batched"] = bench_batched(bm, torch, g, ix)
     if args.config3:
         res["config3"] = bench_config3(bm, torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(g, pts)
     print(json.dumps(res), flush=True)
+
+
+def bench_batched(bm, torch, g, ix, nb=10_000):
+    """Batched form: 10,000 batches over this index, sizes log-uniform on
+    [1, 1e6], each batch one Gaussian cluster (centre uniform, sigma
+    log-uniform on [0.1%, 5%] of the extent). One graph replay (and one eager
+    persistent launch) against one plain launch per batch."""
+    t0 = time.time()
+    sizes = synth.sizes(synth.key(4, 2, 0), nb, 0, 0.0, 0.0, 1e6)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    total = int(off[-1])
+    host = np.empty((total, 2), np.int32)
+    for b in range(nb):
+        m = synth.Mixture(synth.key(4, 2, b + 1), 1, g.W, 0.0, 0.001, 0.05, 0.0)
+        m.sample(synth.key(4, 3, b + 1), 0, int(sizes[b]), out=host[off[b]:off[b + 1]])
+    xy = torch.from_numpy(host).cuda()
+    del host
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    ref = torch.empty(total, dtype=torch.int32, device="cuda")
+    log("batched: %d batches, %d points (sizes %d..%d), generated in %.1fs" %
+        (nb, total, sizes.min(), sizes.max(), time.time() - t0))
+    base_x, base_o, base_r = xy.data_ptr(), out.data_ptr(), ref.data_ptr()
+    rows = [(base_x + 8 * int(off[b]), base_o + 4 * int(off[b]), int(sizes[b])) for b in range(nb)]
+    s = torch.cuda.current_stream()
+    tune = bm.autotune(ix, xy[: min(total, 1 << 22)], s)
+    log("batched: autotuned %s" % tune.as_dict())
+    # per-batch plain launches (the library's plain entry point, one call per batch)
+    lib, sh = bm.lib, bm._stream_handle(s)
+    import ctypes as C
+
+    def plain_all():
+        for b in range(nb):
+            lib.map_points(ix.handle, C.c_void_p(base_x + 8 * int(off[b])), int(sizes[b]),
+                           C.c_void_p(base_r + 4 * int(off[b])), sh)
+    plain_all()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain_all()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    # eager persistent launch over a device table
+    table = torch.tensor(rows, dtype=torch.int64).cuda()
+    bm.map_batches(ix, table, s, tune)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = time.perf_counter()
+    e0.record(s)
+    bm.map_batches(ix, table, s, tune)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t
+    eager_ms = e0.elapsed_time(e1)
+    ok_eager = bool(torch.equal(out, ref))
+    # captured graph, replayed
+    out.fill_(-7)
+    plan = bm.BatchPlan(ix, nb, tune)
+    crow = bm.make_rows(rows)
+    plan.run_rows(crow, nb, s)
+    torch.cuda.synchronize()
+    ok_graph = bool(torch.equal(out, ref))
+    reps = 3
+    t = time.perf_counter()
+    e0.record(s)
+    for _ in range(reps):
+        plan.run_rows(crow, nb, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t) / reps
+    graph_ms = e0.elapsed_time(e1) / reps
+    plan.close()
+    res = {"batches": nb, "points": total, "tuning": tune.as_dict(),
+           "graph_points_per_s": total / t_graph, "graph_ms": graph_ms,
+           "eager_points_per_s": total / t_eager, "eager_kernel_ms": eager_ms,
+           "plain_per_batch_points_per_s": total / t_plain, "plain_per_batch_ms": t_plain * 1e3,
+           "identical_to_plain": ok_eager and ok_graph,
+           "hbm_frac": BYTES_PER_POINT * total / (graph_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    log("batched: graph %.1f ms (%.3g pts/s), eager %.1f ms, per-batch plain %.1f ms (%.3g pts/s), identical=%s" %
+        (graph_ms, res["graph_points_per_s"], eager_ms, t_plain * 1e3, res["plain_per_batch_points_per_s"],
+         res["identical_to_plain"]))
+    del xy, out, ref, table
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_config3(bm, torch):

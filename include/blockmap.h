@@ -151,8 +151,10 @@ int bm_quantize_lonlat(const double* lonlat, int64_t n, int32_t* xy, hipStream_t
 typedef struct {
   int32_t edge_chunk;       /* ring edges per crossing-test work item: 4, 8 or 16 */
   int32_t blocks_per_cu;    /* resident workgroups per compute unit (1..8) */
-  int32_t tile_points;      /* points per scheduling tile in the batched form (multiple of 256) */
+  int32_t tile_points;      /* batched form: points per unit of work (multiple of 64, <= 2^20) */
 } bm_tuning;
+
+/* Out-of-range fields are replaced by their defaults. */
 
 /* Fill *t with the defaults used when a tuning pointer is null. */
 int bm_tuning_default(bm_tuning* t);
@@ -160,6 +162,57 @@ int bm_tuning_default(bm_tuning* t);
 /* As map_points, with an explicit launch shape (t may be null). */
 int map_points_tuned(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
                      const bm_tuning* t, hipStream_t stream);
+
+/* Pick a launch shape by timing candidates on a sample of points (device
+ * pointer, n >= 64) with this index; the choice is cached per (device
+ * architecture, index shape, size class) in the file named by the environment
+ * variable BM_TUNE_CACHE (default $HOME/.cache/blockmap_tune.txt; unreadable or
+ * unwritable cache files are ignored). Runs and synchronises on `stream`.
+ * Errors: BM_EINVAL, BM_EHIP. */
+int bm_autotune(const bm_index* index, const int32_t* sample_xy, int64_t n, bm_tuning* out,
+                hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: many independent point batches of uneven size in one      */
+/* persistent launch (the data-parallel split of the paper's Sec. V, on one */
+/* device). Results are identical to one map_points call per batch.         */
+/* ------------------------------------------------------------------------ */
+
+/* One batch: device pointers to n interleaved (x, y) points and n outputs. */
+typedef struct {
+  const int32_t* xy;
+  int32_t* out_ids;
+  int64_t n;
+} bm_batch;
+
+/* Map nb batches with one persistent kernel. `batches` is a DEVICE array of
+ * nb descriptors (the caller keeps it alive until the stream has passed this
+ * call); their pointers must be valid device pointers for n points, and a
+ * descriptor with n <= 0 is skipped. Work units of tuning->tile_points points
+ * are taken from a device counter by the resident waves, so uneven batches
+ * balance. Uses nb + 3 int64 of stream-ordered device scratch
+ * (hipMallocAsync / hipFreeAsync on `stream`). Asynchronous. Batches must not
+ * overlap each other's outputs.
+ * Errors: BM_EINVAL (null index or table, nb < 0), BM_ENOMEM, BM_EHIP. */
+int bm_map_batches(const bm_index* index, const bm_batch* batches, int64_t nb, const bm_tuning* t,
+                   hipStream_t stream);
+
+/* The same as a captured HIP graph, for repeated use, with the batch table
+ * given on the HOST (and checked there: n >= 0, non-null pointers when
+ * n > 0): the plan owns a device batch table for up to max_batches batches
+ * and a pinned staging copy; the
+ * graph (table upload, work-unit prefix, persistent mapping kernel) is
+ * captured once at creation and replayed by bm_batch_plan_run, which only
+ * rewrites the staging table. A run waits for the previous run of the same
+ * plan to finish before touching the staging table; different plans are
+ * independent. */
+typedef struct bm_batch_plan bm_batch_plan;
+
+int bm_batch_plan_create(const bm_index* index, int64_t max_batches, const bm_tuning* t,
+                         bm_batch_plan** out);
+/* Errors: BM_EINVAL (nb > max_batches, bad descriptors), BM_EHIP. */
+int bm_batch_plan_run(bm_batch_plan* plan, const bm_batch* batches, int64_t nb, hipStream_t stream);
+void bm_batch_plan_destroy(bm_batch_plan* plan);
 
 /* Error text for the last failing call on this thread ("" if none). */
 const char* bm_last_error(void);

@@ -52,6 +52,10 @@ class Tuning(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class Batch(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("out_ids", C.c_void_p), ("n", C.c_int64)]
+
+
 _P, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32
 _SIGS = {
     "bm_index_create": (C.c_int, [C.POINTER(IndexDesc), C.POINTER(C.c_void_p)]),
@@ -63,6 +67,11 @@ _SIGS = {
     "map_points_tuned": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P]),
     "bm_quantize_lonlat": (C.c_int, [_P, _I64, _P, _P]),
     "bm_tuning_default": (C.c_int, [C.POINTER(Tuning)]),
+    "bm_autotune": (C.c_int, [_P, _P, _I64, C.POINTER(Tuning), _P]),
+    "bm_map_batches": (C.c_int, [_P, _P, _I64, C.POINTER(Tuning), _P]),
+    "bm_batch_plan_create": (C.c_int, [_P, _I64, C.POINTER(Tuning), C.POINTER(C.c_void_p)]),
+    "bm_batch_plan_run": (C.c_int, [_P, C.POINTER(Batch), _I64, _P]),
+    "bm_batch_plan_destroy": (None, [_P]),
     "bm_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -185,6 +194,81 @@ def quantize_lonlat(lonlat, out=None, stream=None):
     _check(lib.bm_quantize_lonlat(_dev_ptr(lonlat, "float64", (2,)), n, _dev_ptr(out, "int32", (2,)),
                                   _stream_handle(stream)))
     return out
+
+
+def autotune(index: Index, sample_xy, stream=None) -> Tuning:
+    """Launch shape picked by timing on a sample (int32 CUDA tensor [n, 2])."""
+    t = Tuning()
+    _check(lib.bm_autotune(index.handle, _dev_ptr(sample_xy, "int32", (2,)), sample_xy.shape[0],
+                           C.byref(t), _stream_handle(stream)))
+    return t
+
+
+def _batch_rows(xys, outs):
+    if len(xys) != len(outs):
+        raise ValueError("xys and outs differ in length")
+    rows = []
+    for xy, out in zip(xys, outs):
+        n = xy.shape[0]
+        if out.shape[0] != n:
+            raise ValueError("an output has the wrong length")
+        rows.append((_dev_ptr(xy, "int32", (2,)).value or 0, _dev_ptr(out, "int32").value or 0, n))
+    return rows
+
+
+def make_rows(rows):
+    """ctypes Batch array from (xy pointer, out pointer, n) triples."""
+    return (Batch * max(len(rows), 1))(*[Batch(a, b, n) for a, b, n in rows])
+
+
+def batch_table(xys, outs, device=None):
+    """Device table of (xy, out, n) descriptors for map_batches (int64 [nb, 3])."""
+    import torch
+    rows = _batch_rows(xys, outs)
+    dev = device if device is not None else (xys[0].device if xys else "cuda")
+    return torch.tensor(rows if rows else [[0, 0, 0]], dtype=torch.int64)[: len(rows)].to(dev)
+
+
+def map_batches(index: Index, table, stream=None, tuning: Tuning | None = None) -> None:
+    """Map every batch of a device table built by batch_table() in one launch."""
+    import torch
+    if not (isinstance(table, torch.Tensor) and table.is_cuda and table.dtype == torch.int64
+            and table.dim() == 2 and table.shape[1] == 3 and table.is_contiguous()):
+        raise TypeError("table must be a contiguous int64 CUDA tensor [nb, 3]")
+    nb = table.shape[0]
+    _check(lib.bm_map_batches(index.handle, C.c_void_p(table.data_ptr()) if nb else None, nb,
+                              C.byref(tuning) if tuning is not None else None, _stream_handle(stream)))
+
+
+class BatchPlan:
+    """Batched form as a captured HIP graph, replayed with a new host table."""
+
+    def __init__(self, index: Index, max_batches: int, tuning: Tuning | None = None):
+        self._index = index  # keep alive
+        h = C.c_void_p()
+        _check(lib.bm_batch_plan_create(index.handle, max_batches,
+                                        C.byref(tuning) if tuning is not None else None, C.byref(h)))
+        self._h = h
+        self.max_batches = max_batches
+
+    def run(self, xys, outs, stream=None) -> None:
+        rows = _batch_rows(xys, outs)
+        self.run_rows(make_rows(rows), len(rows), stream)
+
+    def run_rows(self, rows, nb: int, stream=None) -> None:
+        """Replay with a prebuilt ctypes Batch array (see make_rows)."""
+        _check(lib.bm_batch_plan_run(self._h, rows, nb, _stream_handle(stream)))
+
+    def close(self) -> None:
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib.bm_batch_plan_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def exported_symbols():

@@ -28,11 +28,12 @@ void clear_error() { g_err.clear(); }
 const char* error_text() { return g_err.c_str(); }
 
 Tuning tuning_from(const bm_tuning* t) {
-  Tuning r{8, 6, 1 << 16};
+  Tuning r{8, 6, 2048};
   if (t) {
     if (t->edge_chunk == 4 || t->edge_chunk == 8 || t->edge_chunk == 16) r.edge_chunk = t->edge_chunk;
     if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 8) r.blocks_per_cu = t->blocks_per_cu;
-    if (t->tile_points >= 256 && t->tile_points % 256 == 0) r.tile_points = t->tile_points;
+    if (t->tile_points >= 64 && t->tile_points <= (1 << 20) && t->tile_points % 64 == 0)
+      r.tile_points = t->tile_points;
   }
   return r;
 }

@@ -34,10 +34,18 @@ struct KIndex {
   int4 root_box;             // union of the level-0 boxes
 };
 
+// One batch of the batched form, as laid out in device memory (identical to
+// the public bm_batch).
+struct BatchEntry {
+  const int32_t* xy;
+  int32_t* out;
+  int64_t n;
+};
+
 struct Tuning {
   int edge_chunk;     // 4, 8 or 16
   int blocks_per_cu;  // 1..8
-  int tile_points;    // batched form scheduling tile
+  int tile_points;    // batched form: points per unit of work taken from the counter (multiple of 64)
 };
 
 Tuning tuning_from(const bm_tuning* t);
@@ -45,6 +53,9 @@ Tuning tuning_from(const bm_tuning* t);
 // Launchers (map_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
                       const Tuning& t, int num_cu, hipStream_t stream);
+// Batched form: meta must hold nb + 3 int64 (nb, work counter, prefix).
+hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, const BatchEntry* tab,
+                          long long* meta, const Tuning& t, int num_cu, hipStream_t stream);
 hipError_t launch_quantize(const double* lonlat, int64_t n, int32_t* xy, int num_cu,
                            hipStream_t stream);
 

@@ -18,6 +18,8 @@
 // which gives the same exact answer.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace bm {
@@ -195,107 +197,183 @@ __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, c
   }
 }
 
+// The whole path for one tile of up to 64 points (one per lane); all 64
+// lanes of the wave take part. Writes out[lane] for lanes below nvalid.
+template <int kChunkShift>
+__device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int lane,
+                                         const int2* __restrict__ xy, const int nvalid,
+                                         int* __restrict__ out) {
+  constexpr int kChunk = 1 << kChunkShift;
+  const bool valid = lane < nvalid;
+  const int2 p = valid ? xy[lane] : make_int2(0, 0);
+  S.pts[lane] = p;
+  S.best[lane] = 0xFFFFFFFFu;
+  S.ovf[lane] = 0;
+  wave_sync();
+
+  // ---- the root's children (level 0), one item per point
+  int cur = 0;
+  unsigned cnt = 0;
+  expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt);
+  cnt = min(cnt, (unsigned)kCap);
+  wave_sync();
+
+  // ---- lower levels: children of the surviving groups
+  for (int l = 0; l < ix.n_levels; ++l) {
+    const int nxt = cur ^ 1;
+    unsigned ncnt = 0;
+    for (unsigned r = 0; r < cnt; r += kWave) {
+      const unsigned q = r + lane;
+      const bool has = q < cnt;
+      const unsigned node = has ? S.node[cur][q] : 0u;
+      const int pl = has ? S.lane[cur][q] : 0;
+      int4 ci = make_int4(0, 0, -1, 0), gb = make_int4(0, 0, 0, 0);
+      if (has) {
+        ci = ix.child[node];
+        gb = ix.box[node];
+      }
+      expand(ix, S, has, ci, gb, S.pts[pl], pl, nxt, ncnt);
+    }
+    cnt = min(ncnt, (unsigned)kCap);
+    cur = nxt;
+    wave_sync();
+  }
+
+  // ---- crossing-number test on the (leaf, point) pairs of list `cur`,
+  // 64 pairs per round; each pair's ring edges are cut into chunks of
+  // kChunk edges and all chunks of the round are dealt across the lanes.
+  for (unsigned r = 0; r < cnt; r += kWave) {
+    const unsigned q = r + lane;
+    const bool has = q < cnt;
+    long long v0 = 0, v1 = 0;
+    unsigned bid = 0;
+    if (has) {
+      const int leaf = (int)S.node[cur][q] - ix.leaf_base;
+      v0 = ix.vert_off[leaf];
+      v1 = ix.vert_off[leaf + 1] - 1;  // index of the closing copy
+      bid = (unsigned)ix.leaf_id[leaf];
+    }
+    const unsigned long long nch = has ? (unsigned long long)((v1 - v0 + kChunk - 1) >> kChunkShift) : 0ull;
+    const unsigned long long incl = wave_incl_scan(nch, lane);
+    const unsigned long long start = incl - nch;
+    const unsigned long long total = __shfl(incl, kWave - 1);
+    S.par[lane] = 0;
+    for (unsigned long long w = 0; w < total; w += kCapChunk) {
+      const unsigned long long a = max(start, w), b = min(start + nch, w + (unsigned long long)kCapChunk);
+      for (unsigned long long c = a; c < b; ++c) {
+        const long long j0 = v0 + (long long)((c - start) << kChunkShift);
+        S.ch_j0[c - w] = (unsigned long long)j0;
+        S.ch_q[c - w] = (unsigned char)lane;
+        S.ch_n[c - w] = (unsigned char)min((long long)kChunk, v1 - j0);
+      }
+      wave_sync();
+      const unsigned nw = (unsigned)min((unsigned long long)kCapChunk, total - w);
+      for (unsigned c = lane; c < nw; c += kWave) {
+        const long long j0 = (long long)S.ch_j0[c];
+        const int ne = S.ch_n[c];
+        const unsigned pq = S.ch_q[c];
+        int2 v[kChunk + 1];
+#pragma unroll
+        for (int u = 0; u <= kChunk; ++u) v[u] = (u <= ne) ? ix.verts[j0 + u] : make_int2(0, 0);
+        const int2 pp = S.pts[S.lane[cur][r + pq]];
+        unsigned acc = 0;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) acc ^= (u < ne) ? crosses(v[u], v[u + 1], pp) : 0u;
+        if (acc) atomicXor(&S.par[pq], 1u);
+      }
+      wave_sync();
+    }
+    if (has && (S.par[lane] & 1u)) atomicMin(&S.best[S.lane[cur][q]], bid);
+    wave_sync();
+  }
+
+  unsigned best = S.best[lane];
+  if (valid && S.ovf[lane]) best = min(best, walk_point(ix, p));
+  if (valid) out[lane] = (int)best;
+  wave_sync();
+}
+
+// Plain form: the waves of the grid stride over the 64-point tiles.
 template <int kChunkShift>
 __global__ __launch_bounds__(kBlock) void map_kernel(const KIndex ix, const int2* __restrict__ xy,
                                                      const long long n, int* __restrict__ out) {
-  constexpr int kChunk = 1 << kChunkShift;
   __shared__ WaveLds wl[kWavesPerBlock];
-
   const int lane = threadIdx.x & (kWave - 1);
   WaveLds& S = wl[threadIdx.x / kWave];
-
   const long long ntiles = (n + kWave - 1) / kWave;
   const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
   for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
        t += nwaves) {
-    const long long i = t * kWave + lane;
-    const bool valid = i < n;
-    const int2 p = valid ? xy[i] : make_int2(0, 0);
-    S.pts[lane] = p;
-    S.best[lane] = 0xFFFFFFFFu;
-    S.ovf[lane] = 0;
-    wave_sync();
+    const long long i0 = t * kWave;
+    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kWave, n - i0), out + i0);
+  }
+}
 
-    // ---- the root's children (level 0), one item per point
-    int cur = 0;
-    unsigned cnt = 0;
-    expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt);
-    cnt = min(cnt, (unsigned)kCap);
-    wave_sync();
-
-    // ---- lower levels: children of the surviving groups
-    for (int l = 0; l < ix.n_levels; ++l) {
-      const int nxt = cur ^ 1;
-      unsigned ncnt = 0;
-      for (unsigned r = 0; r < cnt; r += kWave) {
-        const unsigned q = r + lane;
-        const bool has = q < cnt;
-        const unsigned node = has ? S.node[cur][q] : 0u;
-        const int pl = has ? S.lane[cur][q] : 0;
-        int4 ci = make_int4(0, 0, -1, 0), gb = make_int4(0, 0, 0, 0);
-        if (has) {
-          ci = ix.child[node];
-          gb = ix.box[node];
-        }
-        expand(ix, S, has, ci, gb, S.pts[pl], pl, nxt, ncnt);
-      }
-      cnt = min(ncnt, (unsigned)kCap);
-      cur = nxt;
-      wave_sync();
+// Batched form. The batch table holds `nb` (xy, out, n) entries in device
+// memory. batch_prefix_kernel writes meta[0] = nb, clears the work counter
+// meta[1] and writes meta[2 + b] = number of work units (`unit` points each,
+// a multiple of 64) before batch b. nb comes from hdr[0] when hdr is given
+// (the graph form stages it with the table), else from nb_arg. Persistent
+// waves of batch_map_kernel then take units from the counter until none is
+// left, so batches of very uneven size balance across the machine.
+__global__ __launch_bounds__(1024) void batch_prefix_kernel(const long long* __restrict__ hdr,
+                                                            const long long nb_arg,
+                                                            const BatchEntry* __restrict__ tab,
+                                                            long long* __restrict__ meta,
+                                                            const int unit) {
+  __shared__ long long part[1024];
+  const long long nb = hdr ? hdr[0] : nb_arg;
+  long long* prefix = meta + 2;
+  long long carry = 0;
+  if (threadIdx.x == 0) {
+    meta[0] = nb;
+    meta[1] = 0;
+    prefix[0] = 0;
+  }
+  for (long long base = 0; base < nb; base += 1024) {
+    const long long b = base + threadIdx.x;
+    const long long n = b < nb ? (long long)tab[b].n : 0;
+    part[threadIdx.x] = n > 0 ? (n + unit - 1) / unit : 0;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
+      const long long t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += t;
+      __syncthreads();
     }
+    if (b < nb) prefix[b + 1] = carry + part[threadIdx.x];
+    carry += part[1023];
+    __syncthreads();
+  }
+}
 
-    // ---- crossing-number test on the (leaf, point) pairs of list `cur`,
-    // 64 pairs per round; each pair's ring edges are cut into chunks of
-    // kChunk edges and all chunks of the round are dealt across the lanes.
-    for (unsigned r = 0; r < cnt; r += kWave) {
-      const unsigned q = r + lane;
-      const bool has = q < cnt;
-      long long v0 = 0, v1 = 0;
-      unsigned bid = 0;
-      if (has) {
-        const int leaf = (int)S.node[cur][q] - ix.leaf_base;
-        v0 = ix.vert_off[leaf];
-        v1 = ix.vert_off[leaf + 1] - 1;  // index of the closing copy
-        bid = (unsigned)ix.leaf_id[leaf];
-      }
-      const unsigned long long nch = has ? (unsigned long long)((v1 - v0 + kChunk - 1) >> kChunkShift) : 0ull;
-      const unsigned long long incl = wave_incl_scan(nch, lane);
-      const unsigned long long start = incl - nch;
-      const unsigned long long total = __shfl(incl, kWave - 1);
-      S.par[lane] = 0;
-      for (unsigned long long w = 0; w < total; w += kCapChunk) {
-        const unsigned long long a = max(start, w), b = min(start + nch, w + (unsigned long long)kCapChunk);
-        for (unsigned long long c = a; c < b; ++c) {
-          const long long j0 = v0 + (long long)((c - start) << kChunkShift);
-          S.ch_j0[c - w] = (unsigned long long)j0;
-          S.ch_q[c - w] = (unsigned char)lane;
-          S.ch_n[c - w] = (unsigned char)min((long long)kChunk, v1 - j0);
-        }
-        wave_sync();
-        const unsigned nw = (unsigned)min((unsigned long long)kCapChunk, total - w);
-        for (unsigned c = lane; c < nw; c += kWave) {
-          const long long j0 = (long long)S.ch_j0[c];
-          const int ne = S.ch_n[c];
-          const unsigned pq = S.ch_q[c];
-          int2 v[kChunk + 1];
-#pragma unroll
-          for (int u = 0; u <= kChunk; ++u) v[u] = (u <= ne) ? ix.verts[j0 + u] : make_int2(0, 0);
-          const int2 pp = S.pts[S.lane[cur][r + pq]];
-          unsigned acc = 0;
-#pragma unroll
-          for (int u = 0; u < kChunk; ++u) acc ^= (u < ne) ? crosses(v[u], v[u + 1], pp) : 0u;
-          if (acc) atomicXor(&S.par[pq], 1u);
-        }
-        wave_sync();
-      }
-      if (has && (S.par[lane] & 1u)) atomicMin(&S.best[S.lane[cur][q]], bid);
-      wave_sync();
+template <int kChunkShift>
+__global__ __launch_bounds__(kBlock) void batch_map_kernel(const KIndex ix, const BatchEntry* __restrict__ tab,
+                                                           long long* __restrict__ meta, const int unit) {
+  __shared__ WaveLds wl[kWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  WaveLds& S = wl[threadIdx.x / kWave];
+  const long long nb = meta[0];
+  const long long* prefix = meta + 2;
+  unsigned long long* counter = reinterpret_cast<unsigned long long*>(meta + 1);
+  const long long total = prefix[nb];
+  for (;;) {
+    unsigned long long u = 0;
+    if (lane == 0) u = atomicAdd(counter, 1ull);
+    u = __shfl(u, 0);
+    if ((long long)u >= total) break;
+    // batch holding unit u: the last b with prefix[b] <= u
+    long long lo = 0, hi = nb - 1;
+    while (lo < hi) {
+      const long long mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= (long long)u) lo = mid; else hi = mid - 1;
     }
-
-    unsigned best = S.best[lane];
-    if (valid && S.ovf[lane]) best = min(best, walk_point(ix, p));
-    if (valid) out[i] = (int)best;
-    wave_sync();
+    const BatchEntry d = tab[lo];
+    const int2* bxy = reinterpret_cast<const int2*>(d.xy);
+    const long long p0 = ((long long)u - prefix[lo]) * unit;
+    const long long p1 = min(p0 + unit, (long long)d.n);
+    for (long long i0 = p0; i0 < p1; i0 += kWave)
+      map_tile<kChunkShift>(ix, S, lane, bxy + i0, (int)min((long long)kWave, p1 - i0), d.out + i0);
   }
 }
 
@@ -333,6 +411,26 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
       break;
     default:
       hipLaunchKernelGGL(map_kernel<3>, grid, block, 0, stream, ix, p, (long long)n, out);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, const BatchEntry* tab,
+                          long long* meta, const Tuning& t, int num_cu, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_prefix_kernel, dim3(1), dim3(1024), 0, stream, hdr, nb, tab, meta, t.tile_points);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)std::max(1, num_cu * t.blocks_per_cu)), block(kBlock);
+  switch (t.edge_chunk) {
+    case 4:
+      hipLaunchKernelGGL(batch_map_kernel<2>, grid, block, 0, stream, ix, tab, meta, t.tile_points);
+      break;
+    case 16:
+      hipLaunchKernelGGL(batch_map_kernel<4>, grid, block, 0, stream, ix, tab, meta, t.tile_points);
+      break;
+    default:
+      hipLaunchKernelGGL(batch_map_kernel<3>, grid, block, 0, stream, ix, tab, meta, t.tile_points);
       break;
   }
   return hipGetLastError();

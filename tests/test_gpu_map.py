@@ -294,3 +294,73 @@ def test_config3_streamed_billion_points(torch_cuda, bm):
         if k == 0:
             assert (got[:8_000_000] == H.map(pts[:8_000_000])).all()
         say("config3 chunk", k, "ok", n)
+
+
+# ------------------------------------------------------- batched form ----
+
+def _cluster_batches(g, sizes, seed):
+    """One Gaussian cluster per batch (the batched workload's recipe)."""
+    out = []
+    for b, n in enumerate(sizes):
+        m = synth.Mixture(synth.key(4, 2, seed * 100000 + b), 1, g.W, 0.0, 0.001, 0.05, 0.0)
+        out.append(m.sample(synth.key(4, 3, seed * 100000 + b), 0, int(n)))
+    return out
+
+
+def test_batched_equals_plain_per_batch(torch_cuda, bm, cfg2):
+    torch = torch_cuda
+    g, ix, H = cfg2
+    sizes = synth.sizes(synth.key(4, 2, 0), 300, 0, 0, 0, 200_000)
+    sizes[:5] = [0, 1, 63, 64, 65]
+    say("batched: %d batches, %d points" % (len(sizes), sizes.sum()))
+    pts = _cluster_batches(g, sizes, 1)
+    xys = [torch.from_numpy(p).cuda() for p in pts]
+    want = [bm.map_points(ix, xy) for xy in xys]
+    torch.cuda.synchronize()
+    for tile in (64, 1024, 8192):
+        outs = [torch.full((p.shape[0],), -7, dtype=torch.int32, device="cuda") for p in pts]
+        tab = bm.batch_table(xys, outs)
+        bm.map_batches(ix, tab, tuning=bm.Tuning(8, 4, tile))
+        torch.cuda.synchronize()
+        for w, o in zip(want, outs):
+            assert torch.equal(w, o), tile
+    allp = np.concatenate(pts)
+    sub = np.random.default_rng(3).choice(allp.shape[0], 20000, replace=False)
+    got = torch.cat(want).cpu().numpy()
+    assert (got[sub] == H.map(allp[sub])).all()
+
+
+def test_batch_plan_graph_replays(torch_cuda, bm, cfg2):
+    """Captured graph replayed with different tables; eager work and syncs in
+    between; every replay equals the plain result."""
+    torch = torch_cuda
+    g, ix, H = cfg2
+    plan = bm.BatchPlan(ix, 64, bm.Tuning(8, 4, 512))
+    for rep in range(4):
+        sizes = synth.sizes(synth.key(4, 2, 10 + rep), 10 + 13 * rep, 0, 0, 0, 50_000)
+        say("plan replay", rep, len(sizes), sizes.sum())
+        pts = _cluster_batches(g, sizes, 20 + rep)
+        xys = [torch.from_numpy(p).cuda() for p in pts]
+        outs = [torch.full((p.shape[0],), -7, dtype=torch.int32, device="cuda") for p in pts]
+        plan.run(xys, outs)
+        torch.cuda.synchronize()
+        for xy, o in zip(xys, outs):
+            assert torch.equal(bm.map_points(ix, xy), o), rep
+        torch.cuda.synchronize()
+    with pytest.raises(bm.BlockmapError):
+        plan.run([xys[0]] * 65, [outs[0]] * 65)
+    plan.close()
+
+
+def test_autotune_never_changes_results(torch_cuda, bm, cfg2, tmp_path, monkeypatch):
+    torch = torch_cuda
+    g, ix, H = cfg2
+    monkeypatch.setenv("BM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    pts = synth.points(2, 2_000_000)
+    xy = torch.from_numpy(pts).cuda()
+    say("autotune")
+    t = bm.autotune(ix, xy)
+    assert t.edge_chunk in (4, 8) and 3 <= t.blocks_per_cu <= 6 and t.tile_points in (512, 2048, 8192)
+    t2 = bm.autotune(ix, xy)  # from the cache
+    assert t2.as_dict() == t.as_dict()
+    assert torch.equal(bm.map_points(ix, xy, tuning=t), bm.map_points(ix, xy))
