@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--sweep", action="store_true", help="also time every launch shape (stderr)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--served-requests", type=int, default=20_000)
     ap.add_argument("--config3", action="store_true",
                     help="also measure the 8M-block graded mesh streamed over 1B points (stderr)")
     args = ap.parse_args()
@@ -132,8 +134,14 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         res["batched"] = bench_batched(bm, torch, g, ix)
-    if args.config3:
-        res["config3"] = bench_config3(bm, torch)
+    if args.config3 or not args.no_served:
+        g3 = synth.geometry(3)
+        ix3 = bm.Index.from_geometry(g3)
+        if args.config3:
+            res["config3"] = bench_config3(bm, torch, g3, ix3)
+        if not args.no_served:
+            res["served"] = bench_served(bm, torch, g3, ix3, args.served_requests)
+        ix3.close()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(g, pts)
     print(json.dumps(res), flush=True)
@@ -221,13 +229,74 @@ def bench_batched(bm, torch, g, ix, nb=10_000):
     return res
 
 
-def bench_config3(bm, torch):
+def bench_served(bm, torch, g, ix, nreq):
+    """Served form over the 8M-block graded mesh resident in HBM: requests of
+    lognormal size (median 10k points, sigma 2, at most 10M), each a Gaussian
+    cluster plus 20% uniform points, in page-locked host memory. Baseline: the
+    same request loop with coalescing and overlap switched off (one request
+    per batch, one slot, one stream), i.e. the plain kernel request by
+    request. Both see the same Poisson arrivals at 50% and 90% of the
+    baseline's capacity, and all at once."""
+    t0 = time.time()
+    npool = 1000
+    sizes = synth.sizes(synth.key(5, 2, 0), npool, 1, 10_000.0, 2.0, 10_000_000)
+    pool, outs, ref = [], [], []
+    for r in range(npool):
+        m = synth.Mixture(synth.key(5, 2, r + 1), 1, g.W, 0.0, 0.001, 0.02, 0.2)
+        x = torch.empty((int(sizes[r]), 2), dtype=torch.int32, pin_memory=True).numpy()
+        m.sample(synth.key(5, 3, r + 1), 0, int(sizes[r]), out=x)
+        pool.append(x)
+        outs.append(torch.empty(int(sizes[r]), dtype=torch.int32, pin_memory=True).numpy())
+        ref.append(bm.map_points(ix, torch.from_numpy(x).cuda()).cpu().numpy())
+    rng = np.random.default_rng(5)
+    order = rng.integers(0, npool, nreq)
+    mean_pts = float(sizes[order].mean())
+    reqs = [(pool[i], outs[i]) for i in order]
+    log("served: %d distinct requests (mean %.0f points, max %d), %d submissions, prepared in %.1fs" %
+        (npool, sizes.mean(), sizes.max(), nreq, time.time() - t0))
+
+    def run(cfg, arrivals, nr):
+        for o in outs:
+            o.fill(-7)
+        srv = bm.Server(ix, cfg)
+        t = time.perf_counter()
+        srv.run_trace(reqs[:nr], arrivals[:nr])
+        wall = time.perf_counter() - t
+        st = srv.stats()
+        srv.close()
+        same = all(np.array_equal(outs[i], ref[i]) for i in set(order[:nr].tolist()))
+        return {"points_per_s": st["points_per_s"], "requests_per_s": st["completed"] / wall,
+                "p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
+                "mean_requests_per_batch": st["mean_requests_per_batch"], "batches": st["batches"],
+                "identical_to_alone": bool(same)}
+
+    base_cfg = bm.server_cfg(mem_budget_bytes=2 << 30, max_batch_points=1 << 24, max_slots=1, n_streams=1,
+                             flags=bm.BM_SERVER_ONE_PER_BATCH)
+    srv_cfg = bm.server_cfg(mem_budget_bytes=2 << 30, max_batch_points=1 << 23, max_slots=6, n_streams=4)
+    nsat = min(nreq, 5000)
+    zero = np.zeros(nreq)
+    res = {"requests": nreq, "mean_points_per_request": mean_pts}
+    res["baseline_saturated"] = run(base_cfg, zero, nsat)
+    cap = res["baseline_saturated"]["requests_per_s"]
+    res["server_saturated"] = run(srv_cfg, zero, nreq)
+    for name, frac in (("50pct", 0.5), ("90pct", 0.9)):
+        arr = np.cumsum(rng.exponential(1e6 / (frac * cap), nreq))
+        res["baseline_" + name] = run(base_cfg, arr, nreq)
+        res["server_" + name] = run(srv_cfg, arr, nreq)
+        res["baseline_" + name]["offered_qps"] = res["server_" + name]["offered_qps"] = frac * cap
+    for k, v in res.items():
+        if isinstance(v, dict):
+            log("served %-19s %.3g pts/s, %.0f req/s, p50 %.0f us, p99 %.0f us, %.1f req/batch, identical=%s" %
+                (k, v["points_per_s"], v["requests_per_s"], v["p50_us"], v["p99_us"], v["mean_requests_per_batch"],
+                 v["identical_to_alone"]))
+    return res
+
+
+def bench_config3(bm, torch, g, ix):
     """8M blocks, 1B points streamed in 2^26-point chunks from pinned host
     memory: kernel-only rate (chunk resident) and end-to-end rate with the
     copies overlapped on a second stream."""
     t0 = time.time()
-    g = synth.geometry(3)
-    ix = bm.Index.from_geometry(g)
     info = ix.info()
     q = synth.QUADTREE
     N, CH = q["n_points"], q["chunk"]

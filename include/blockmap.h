@@ -214,6 +214,84 @@ int bm_batch_plan_create(const bm_index* index, int64_t max_batches, const bm_tu
 int bm_batch_plan_run(bm_batch_plan* plan, const bm_batch* batches, int64_t nb, hipStream_t stream);
 void bm_batch_plan_destroy(bm_batch_plan* plan);
 
+/* ------------------------------------------------------------------------ */
+/* Served form: a request loop with continuous batching over a resident     */
+/* index. Requests (host buffers) queue FIFO; a dispatcher thread packs the  */
+/* head of the queue into a device batch as soon as a batch slot and enough  */
+/* pool memory are free (admission by memory), copies it in, maps it and     */
+/* copies it back on one of several streams, so batches overlap on the      */
+/* device; a completion thread scatters results and frees memory. Results    */
+/* are those of map_points on each request alone.                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct bm_server bm_server;
+
+enum {
+  BM_SERVER_FAIL_ALLOC = 1,     /* force the pool allocation to fail (failure-path tests) */
+  BM_SERVER_ONE_PER_BATCH = 2   /* no coalescing: one request piece per batch (with one slot and
+                                   one stream this is the plain kernel request by request) */
+};
+
+typedef struct {
+  int64_t mem_budget_bytes;  /* device pool (and pinned host pool) for in-flight batches; each
+                                point in flight takes 12 bytes (+256-byte alignment per batch) */
+  int64_t max_batch_points;  /* points per device batch; larger requests are split */
+  int32_t max_slots;         /* batches in flight at once (1..64) */
+  int32_t n_streams;         /* streams the batches are spread over (1..16) */
+  int32_t coalesce_us;       /* a batch smaller than max_batch_points may wait this long for
+                                more arrivals (0 = dispatch at once) */
+  int32_t queue_capacity;    /* queued request pieces before submit returns BM_EBUSY */
+  int32_t flags;             /* BM_SERVER_* */
+  bm_tuning tuning;          /* launch shape of the mapping kernel */
+} bm_server_cfg;
+
+int bm_server_cfg_default(bm_server_cfg* cfg);
+
+/* Allocates the pools, streams and two threads. The index must live on the
+ * current device and outlive the server.
+ * Errors: BM_EINVAL (budget below one full batch, fields out of range),
+ * BM_ENOMEM, BM_EHIP. */
+int bm_server_create(const bm_index* index, const bm_server_cfg* cfg, bm_server** out);
+
+/* Queue a request: n points at host address xy, results to host address out
+ * (both must stay valid until the request is waited for). *ticket identifies
+ * it. Buffers in page-locked memory (hipHostMalloc) are copied by DMA
+ * directly; others are packed through the server's pinned pool. Returns BM_EBUSY when the queue is full (nothing is queued then), or the
+ * error of an earlier device failure. */
+int bm_server_submit(bm_server* srv, const int32_t* xy, int64_t n, int32_t* out, uint64_t* ticket);
+
+/* Wait for a request (timeout_us < 0: no limit). BM_OK consumes the ticket;
+ * BM_ETIMEDOUT leaves it pending; an unknown ticket gives BM_EINVAL. */
+int bm_server_wait(bm_server* srv, uint64_t ticket, int64_t timeout_us);
+
+typedef struct {
+  int64_t completed;          /* requests finished */
+  int64_t points;             /* their points */
+  int64_t batches;            /* device batches dispatched */
+  int64_t rejected;           /* submits refused with BM_EBUSY */
+  double mean_requests_per_batch;
+  double p50_us, p99_us, mean_us, max_us;  /* submit-to-completion latency */
+  double points_per_s;        /* points / (last completion - first submit) */
+} bm_server_stats;
+
+int bm_server_get_stats(bm_server* srv, bm_server_stats* out);
+int bm_server_reset_stats(bm_server* srv);
+
+/* Load harness: submit reqs[i] at arrival_us[i] microseconds after the call
+ * (busy-waiting for the time; retrying while the queue is full), then wait
+ * for all of them. Latencies are in bm_server_get_stats. */
+typedef struct {
+  const int32_t* xy;
+  int32_t* out_ids;
+  int64_t n;
+} bm_request;
+
+int bm_server_run_trace(bm_server* srv, const bm_request* reqs, int64_t nreq, const double* arrival_us);
+
+/* Stop the threads after the batches in flight finish; requests still queued
+ * are dropped. No call on the server may be running. */
+void bm_server_destroy(bm_server* srv);
+
 /* Error text for the last failing call on this thread ("" if none). */
 const char* bm_last_error(void);
 

@@ -56,6 +56,30 @@ class Batch(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("out_ids", C.c_void_p), ("n", C.c_int64)]
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_int64), ("max_batch_points", C.c_int64), ("max_slots", C.c_int32),
+                ("n_streams", C.c_int32), ("coalesce_us", C.c_int32), ("queue_capacity", C.c_int32),
+                ("flags", C.c_int32), ("tuning", Tuning)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("points", C.c_int64), ("batches", C.c_int64),
+                ("rejected", C.c_int64), ("mean_requests_per_batch", C.c_double), ("p50_us", C.c_double),
+                ("p99_us", C.c_double), ("mean_us", C.c_double), ("max_us", C.c_double),
+                ("points_per_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
+class Request(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("out_ids", C.c_void_p), ("n", C.c_int64)]
+
+
+BM_SERVER_FAIL_ALLOC = 1
+BM_SERVER_ONE_PER_BATCH = 2
+
 _P, _I64, _I32 = C.c_void_p, C.c_int64, C.c_int32
 _SIGS = {
     "bm_index_create": (C.c_int, [C.POINTER(IndexDesc), C.POINTER(C.c_void_p)]),
@@ -72,6 +96,14 @@ _SIGS = {
     "bm_batch_plan_create": (C.c_int, [_P, _I64, C.POINTER(Tuning), C.POINTER(C.c_void_p)]),
     "bm_batch_plan_run": (C.c_int, [_P, C.POINTER(Batch), _I64, _P]),
     "bm_batch_plan_destroy": (None, [_P]),
+    "bm_server_cfg_default": (C.c_int, [C.POINTER(ServerCfg)]),
+    "bm_server_create": (C.c_int, [_P, C.POINTER(ServerCfg), C.POINTER(C.c_void_p)]),
+    "bm_server_submit": (C.c_int, [_P, _P, _I64, _P, C.POINTER(C.c_uint64)]),
+    "bm_server_wait": (C.c_int, [_P, C.c_uint64, _I64]),
+    "bm_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
+    "bm_server_reset_stats": (C.c_int, [_P]),
+    "bm_server_run_trace": (C.c_int, [_P, C.POINTER(Request), _I64, _P]),
+    "bm_server_destroy": (None, [_P]),
     "bm_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -263,6 +295,70 @@ class BatchPlan:
         h, self._h = getattr(self, "_h", None), None
         if h:
             lib.bm_batch_plan_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_cfg(**kw) -> ServerCfg:
+    c = ServerCfg()
+    _check(lib.bm_server_cfg_default(C.byref(c)))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """Continuous-batching request loop over a resident index (host buffers)."""
+
+    def __init__(self, index: Index, cfg: ServerCfg | None = None):
+        self._index = index
+        h = C.c_void_p()
+        _check(lib.bm_server_create(index.handle, C.byref(cfg) if cfg is not None else None, C.byref(h)))
+        self._h = h
+
+    def submit(self, xy: np.ndarray, out: np.ndarray) -> int:
+        """Queue int32 [n, 2] points; results land in int32 [n] `out` (both
+        numpy arrays, kept alive by the caller until wait())."""
+        assert xy.dtype == np.int32 and xy.flags.c_contiguous and xy.ndim == 2 and xy.shape[1] == 2
+        assert out.dtype == np.int32 and out.flags.c_contiguous and out.shape == (xy.shape[0],)
+        t = C.c_uint64()
+        _check(lib.bm_server_submit(self._h, xy.ctypes.data if xy.size else None, xy.shape[0],
+                                    out.ctypes.data if out.size else None, C.byref(t)))
+        return t.value
+
+    def try_submit(self, xy, out):
+        try:
+            return self.submit(xy, out)
+        except BlockmapError as e:
+            if e.code == BM_EBUSY:
+                return None
+            raise
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> None:
+        _check(lib.bm_server_wait(self._h, ticket, timeout_us))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib.bm_server_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self) -> None:
+        _check(lib.bm_server_reset_stats(self._h))
+
+    def run_trace(self, reqs, arrival_us) -> None:
+        """reqs: list of (xy, out) numpy pairs; arrival_us: float64 offsets."""
+        arr = (Request * max(len(reqs), 1))(*[Request(x.ctypes.data, o.ctypes.data, x.shape[0]) for x, o in reqs])
+        at = np.ascontiguousarray(arrival_us, np.float64)
+        _check(lib.bm_server_run_trace(self._h, arr, len(reqs), at.ctypes.data))
+
+    def close(self) -> None:
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib.bm_server_destroy(h)
 
     def __del__(self):
         try:

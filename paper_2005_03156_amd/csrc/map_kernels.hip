@@ -30,7 +30,6 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kCap = 256;       // (node, point) items per list per wave
 constexpr int kCapChunk = 256;  // crossing-test chunks per window per wave
-constexpr unsigned kRoot = 0xFFFFFFFFu;
 
 struct WaveLds {
   int2 pts[kWave];

@@ -364,3 +364,87 @@ def test_autotune_never_changes_results(torch_cuda, bm, cfg2, tmp_path, monkeypa
     t2 = bm.autotune(ix, xy)  # from the cache
     assert t2.as_dict() == t.as_dict()
     assert torch.equal(bm.map_points(ix, xy, tuning=t), bm.map_points(ix, xy))
+
+
+# -------------------------------------------------------- served form ----
+
+def _requests(g, sizes, seed):
+    out = []
+    for r, n in enumerate(sizes):
+        m = synth.Mixture(synth.key(5, 2, seed * 100000 + r), 1, g.W, 0.0, 0.001, 0.02, 0.2)
+        out.append(m.sample(synth.key(5, 3, seed * 100000 + r), 0, int(n)))
+    return out
+
+
+def test_server_results_same_alone_and_in_the_mix(torch_cuda, bm, cfg2):
+    """Requests submitted together, coalesced into shared device batches (and
+    split across batches when large), give exactly the ids each gets alone."""
+    torch = torch_cuda
+    g, ix, H = cfg2
+    sizes = list(synth.sizes(synth.key(5, 2, 0), 300, 1, 2000.0, 1.5, 300_000))
+    sizes[:4] = [0, 1, 64, 250_000]
+    reqs = _requests(g, sizes, 1)
+    alone = [gpu_map(bm, torch, ix, p) for p in reqs]
+    for cfg in (bm.server_cfg(mem_budget_bytes=64 << 20, max_batch_points=100_000, max_slots=4, n_streams=3),
+                bm.server_cfg(mem_budget_bytes=12 * 70_000 + 4096, max_batch_points=70_000, max_slots=2,
+                              n_streams=1, coalesce_us=200)):
+        say("server mix", cfg.max_batch_points, cfg.max_slots, cfg.n_streams)
+        srv = bm.Server(ix, cfg)
+        outs = [np.full(p.shape[0], -7, np.int32) for p in reqs]
+        tickets = [srv.submit(p, o) for p, o in zip(reqs, outs)]
+        for t in tickets:
+            srv.wait(t)
+        st = srv.stats()
+        srv.close()
+        for a, o in zip(alone, outs):
+            assert (a == o).all()
+        assert st["completed"] == len(reqs) and st["p50_us"] <= st["p99_us"] <= st["max_us"]
+        assert st["mean_requests_per_batch"] > 1.0  # requests really shared batches
+
+
+def test_server_backpressure_timeout_and_failure(torch_cuda, bm, cfg2):
+    g, ix, H = cfg2
+    pts = _requests(g, [1000, 1000, 1000], 2)
+    outs = [np.empty(1000, np.int32) for _ in pts]
+    # a long coalescing window keeps the first pieces queued: the queue fills
+    srv = bm.Server(ix, bm.server_cfg(queue_capacity=2, coalesce_us=300_000, max_batch_points=1 << 20))
+    t1 = srv.submit(pts[0], outs[0])
+    t2 = srv.submit(pts[1], outs[1])
+    with pytest.raises(bm.BlockmapError) as e:
+        srv.submit(pts[2], outs[2])
+    assert e.value.code == bm.BM_EBUSY
+    with pytest.raises(bm.BlockmapError) as e:
+        srv.wait(t1, timeout_us=1000)
+    assert e.value.code == bm.BM_ETIMEDOUT
+    srv.wait(t1)
+    srv.wait(t2)
+    assert (outs[0] == gpu_map(bm, torch_cuda, ix, pts[0])).all()
+    with pytest.raises(bm.BlockmapError) as e:
+        srv.wait(t1)  # consumed
+    assert e.value.code == bm.BM_EINVAL
+    srv.close()
+    with pytest.raises(bm.BlockmapError) as e:
+        bm.Server(ix, bm.server_cfg(flags=bm.BM_SERVER_FAIL_ALLOC))
+    assert e.value.code == bm.BM_ENOMEM
+    with pytest.raises(bm.BlockmapError) as e:
+        bm.Server(ix, bm.server_cfg(mem_budget_bytes=1000, max_batch_points=1000))
+    assert e.value.code == bm.BM_EINVAL
+
+
+def test_server_poisson_trace(torch_cuda, bm, cfg2):
+    g, ix, H = cfg2
+    sizes = synth.sizes(synth.key(5, 2, 7), 2000, 1, 10_000.0, 2.0, 2_000_000)
+    reqs = _requests(g, sizes, 3)
+    outs = [np.full(p.shape[0], -7, np.int32) for p in reqs]
+    rng = np.random.default_rng(0)
+    arrivals = np.cumsum(rng.exponential(1e6 / 5000.0, len(reqs)))  # 5,000 requests/s
+    srv = bm.Server(ix, bm.server_cfg(mem_budget_bytes=256 << 20, max_batch_points=1 << 21))
+    say("server trace", len(reqs), int(sizes.sum()))
+    srv.run_trace(list(zip(reqs, outs)), arrivals)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs)
+    allp = np.concatenate(reqs)
+    allo = np.concatenate(outs)
+    sub = np.random.default_rng(1).choice(allp.shape[0], 50_000, replace=False)
+    assert (allo[sub] == H.map(allp[sub])).all()
