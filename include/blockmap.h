@@ -100,7 +100,7 @@ void bm_index_destroy(bm_index* index);
 
 typedef struct {
   int64_t n_blocks;
-  int64_t n_vertices;      /* as stored on the device (closing copies included) */
+  int64_t n_vertices;      /* ring vertices as given */
   int64_t n_nodes;         /* groups on all levels plus blocks */
   int64_t device_bytes;    /* device memory held by the index */
   int32_t n_levels;        /* group levels */
@@ -117,6 +117,11 @@ int bm_index_get_info(const bm_index* index, bm_index_info* info);
  * BM_ENOMEM, BM_EHIP. */
 int bm_index_save(const bm_index* index, const char* path);
 int bm_index_load(const char* path, bm_index** out);
+
+/* Build the index on the host only and write it to `path` in the format of
+ * bm_index_save (no device needed; load it later with bm_index_load).
+ * Errors: those of bm_index_create except BM_EHIP, and BM_EIO. */
+int bm_index_build_file(const bm_index_desc* desc, const char* path);
 
 /* ------------------------------------------------------------------------ */
 /* Plain mapping.                                                           */

@@ -87,6 +87,7 @@ _SIGS = {
     "bm_index_get_info": (C.c_int, [_P, C.POINTER(IndexInfo)]),
     "bm_index_save": (C.c_int, [_P, C.c_char_p]),
     "bm_index_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_void_p)]),
+    "bm_index_build_file": (C.c_int, [C.POINTER(IndexDesc), C.c_char_p]),
     "map_points": (C.c_int, [_P, _P, _I64, _P, _P]),
     "map_points_tuned": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P]),
     "bm_quantize_lonlat": (C.c_int, [_P, _I64, _P, _P]),
@@ -146,6 +147,24 @@ def tuning_default() -> Tuning:
     return t
 
 
+def _desc(vert_off, verts, n_groups, parents):
+    vo = np.ascontiguousarray(vert_off, np.int64)
+    vv = np.ascontiguousarray(verts, np.int32)
+    ng = np.ascontiguousarray(n_groups, np.int64)
+    pars = [np.ascontiguousarray(p, np.int32) for p in parents]
+    parr = (C.c_void_p * max(len(pars), 1))(*[p.ctypes.data for p in pars])
+    d = IndexDesc(vo.shape[0] - 1, vo.ctypes.data, vv.ctypes.data, len(pars),
+                  ng.ctypes.data if len(pars) else None, C.cast(parr, C.c_void_p))
+    return d, (vo, vv, ng, pars, parr)
+
+
+def build_index_file(path: str, vert_off, verts, n_groups=(), parents=()) -> None:
+    """Build an index on the host only and write it to a file (no GPU needed)."""
+    d, keep = _desc(vert_off, verts, n_groups, parents)
+    _check(lib.bm_index_build_file(C.byref(d), os.fsencode(path)))
+    del keep
+
+
 class Index:
     """A block partition and its hierarchy, resident in device memory."""
 
@@ -154,15 +173,10 @@ class Index:
         if _handle is not None:
             self._h = _handle
             return
-        vo = np.ascontiguousarray(vert_off, np.int64)
-        vv = np.ascontiguousarray(verts, np.int32)
-        ng = np.ascontiguousarray(n_groups, np.int64)
-        pars = [np.ascontiguousarray(p, np.int32) for p in parents]
-        parr = (C.c_void_p * max(len(pars), 1))(*[p.ctypes.data for p in pars])
-        d = IndexDesc(vo.shape[0] - 1, vo.ctypes.data, vv.ctypes.data, len(pars),
-                      ng.ctypes.data if len(pars) else None, C.cast(parr, C.c_void_p))
+        d, keep = _desc(vert_off, verts, n_groups, parents)
         h = C.c_void_p()
         _check(lib.bm_index_create(C.byref(d), C.byref(h)))
+        del keep
         self._h = h
 
     @classmethod

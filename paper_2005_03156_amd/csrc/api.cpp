@@ -13,6 +13,7 @@ int index_create(const bm_index_desc* d, bm_index** out);
 void index_destroy(bm_index* ix);
 int index_save(const bm_index* ix, const char* path);
 int index_load(const char* path, bm_index** out);
+int index_build_file(const bm_index_desc* d, const char* path);
 
 namespace {
 thread_local std::string g_err;
@@ -28,7 +29,7 @@ void clear_error() { g_err.clear(); }
 const char* error_text() { return g_err.c_str(); }
 
 Tuning tuning_from(const bm_tuning* t) {
-  Tuning r{8, 6, 2048};
+  Tuning r{4, 5, 2048};
   if (t) {
     if (t->edge_chunk == 4 || t->edge_chunk == 8 || t->edge_chunk == 16) r.edge_chunk = t->edge_chunk;
     if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 8) r.blocks_per_cu = t->blocks_per_cu;
@@ -83,7 +84,7 @@ __attribute__((visibility("default"))) void bm_index_destroy(bm_index* index) {
 __attribute__((visibility("default"))) int bm_index_get_info(const bm_index* ix, bm_index_info* info) {
   if (!ix || !info) return fail(BM_EINVAL, "bm_index_get_info: null argument");
   info->n_blocks = ix->n_blocks;
-  info->n_vertices = ix->n_verts_stored;
+  info->n_vertices = ix->n_verts;
   info->n_nodes = ix->n_nodes;
   info->device_bytes = ix->bytes;
   info->n_levels = ix->k.n_levels;
@@ -98,6 +99,14 @@ __attribute__((visibility("default"))) int bm_index_save(const bm_index* index, 
     return index_save(index, path);
   }
   BM_GUARD("bm_index_save")
+}
+
+__attribute__((visibility("default"))) int bm_index_build_file(const bm_index_desc* desc, const char* path) {
+  try {
+    clear_error();
+    return index_build_file(desc, path);
+  }
+  BM_GUARD("bm_index_build_file")
 }
 
 __attribute__((visibility("default"))) int bm_index_load(const char* path, bm_index** out) {

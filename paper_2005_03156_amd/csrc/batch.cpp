@@ -205,7 +205,7 @@ __attribute__((visibility("default"))) int bm_autotune(const bm_index* index, co
     char key[256];
     const int size_class = (int)std::floor(std::log2((double)n));
     snprintf(key, sizeof key, "%s|blocks=%lld|verts=%lld|levels=%d|top=%d|n=2^%d", prop.gcnArchName,
-             (long long)index->n_blocks, (long long)index->n_verts_stored, index->k.n_levels, index->k.g0,
+             (long long)index->n_blocks, (long long)index->n_verts, index->k.n_levels, index->k.g0,
              size_class);
     const std::string path = cache_path();
     if (FILE* f = fopen(path.c_str(), "r")) {

@@ -15,23 +15,39 @@ namespace bm {
 // blocks ("leaves") come last, [leaf_base, leaf_base + n_leaves). The
 // children of a group node form one contiguous id range, and consecutive
 // groups own consecutive ranges.
+//
+// Records are sized and aligned so that the box a parent level tests and the
+// data the next step needs share a cache line.
+struct alignas(32) GroupRec {
+  int4 box;    // half-open (xmin, xmax, ymin, ymax), the union of the children's boxes
+  int4 child;  // (first child, end of children, offset of the slot table in
+               // slot_mask or -1, log2 slot count | x shift << 8 | y shift << 16)
+};
+
+// A block's ring is reached through y-slabs: its y-extent [ymin, ymax) is cut
+// into K = 2^logK slabs of height 2^sh, and slab s lists, as ready vertex
+// pairs (a.x, a.y, b.x, b.y), the ring edges whose y-span overlaps it.
+struct alignas(64) LeafRec {
+  int4 box;
+  long long ent;       // index in `ent` of the leaf's first listed edge
+  int leaf_id;         // block index as given by the caller
+  int packed;          // sh | logK << 8 | kLeafExtOff when the offsets are not inline
+  unsigned char off[32];  // inline slab offsets (K + 1 <= 32, all <= 255), relative to ent
+};
+constexpr int kLeafExtOff = 1 << 24;  // offsets are K + 1 uint32 stored in the int4s before ent
+
 struct KIndex {
-  const int4* box;           // [n_nodes] half-open (xmin, xmax, ymin, ymax)
-  // [leaf_base] per group node: (first child, end of children, offset of the
-  // group's slot table in `slot_mask` or -1, packed table shape: log2 of the
-  // slot count | x shift << 8 | y shift << 16)
-  const int4* child;
+  const GroupRec* grp;        // [leaf_base]
+  const LeafRec* leaf;        // [n_leaves]
+  const int4* ent;            // slab edge lists (and out-of-line slab offsets)
   const unsigned long long* slot_mask;  // per table: S x-slot masks, then S y-slot masks
-  const int32_t* parent;     // [n_nodes] parent node, -1 on level 0
-  const int64_t* vert_off;   // [n_leaves + 1] ring offsets into verts (leaf order)
-  const int32_t* leaf_id;    // [n_leaves] block index of each leaf as given by the caller
-  const int2* verts;         // rings, each closed by a stored copy of its first vertex
-  int32_t n_levels;          // group levels above the leaves
-  int32_t g0;                // nodes on level 0
-  int32_t leaf_base;         // first leaf node id
+  const int32_t* parent;      // [n_nodes] parent node, -1 on level 0 (fallback walk)
+  int32_t n_levels;           // group levels above the leaves
+  int32_t g0;                 // nodes on level 0
+  int32_t leaf_base;          // first leaf node id
   int32_t n_leaves;
-  int4 root_child;           // the virtual root: its children are level 0
-  int4 root_box;             // union of the level-0 boxes
+  int4 root_child;            // the virtual root: its children are level 0
+  int4 root_box;              // union of the level-0 boxes
 };
 
 // One batch of the batched form, as laid out in device memory (identical to
@@ -72,9 +88,10 @@ struct bm_index {
   int num_cu;
   int64_t n_blocks;
   int64_t n_nodes;
-  int64_t n_verts_stored;
+  int64_t n_verts;   // ring vertices as given (for reporting)
   int64_t n_masks;
+  int64_t n_ent;
   int64_t bytes;
-  void* allocs[12];
+  void* allocs[16];
   int n_allocs;
 };

@@ -1,4 +1,5 @@
-// Index construction: validation, node ordering, half-open boxes, upload.
+// Index construction: validation, node ordering, half-open boxes, slot
+// tables, y-slab edge lists, upload, save/load.
 //
 // The hierarchy of the paper (Sec. III-B: states holding counties holding
 // blocks, each with a bounding box and, for blocks, a polygon) becomes one
@@ -15,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -28,14 +30,22 @@ struct HostIndex {
   int32_t n_levels = 0, g0 = 0, leaf_base = 0, n_leaves = 0;
   int4 root_child = {0, 0, -1, 0};
   int4 root_box = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
-  std::vector<int4> box;
-  std::vector<int4> child;
+  int64_t n_verts = 0;
+  std::vector<GroupRec> grp;
+  std::vector<LeafRec> leaf;
+  std::vector<int4> ent;
   std::vector<uint64_t> slot_mask;
   std::vector<int32_t> parent;
-  std::vector<int64_t> vert_off;
-  std::vector<int32_t> leaf_id;
-  std::vector<int2> verts;
 };
+
+const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+
+inline void grow(int4& a, const int4& b) {
+  a.x = std::min(a.x, b.x);
+  a.y = std::max(a.y, b.y);
+  a.z = std::min(a.z, b.z);
+  a.w = std::max(a.w, b.w);
+}
 
 // Slot table of a group with 6..64 children: the group box is cut into S
 // equal power-of-two slots per axis (S = 8 up to 16 children, else 16), and
@@ -43,8 +53,8 @@ struct HostIndex {
 // axis. For a point in the group box, (x-slot mask & y-slot mask) is a superset
 // of the children whose boxes contain it; the exact half-open box test is then
 // run on those children only, so the filter's result is unchanged.
-int4 make_table(const std::vector<int4>& box, int c0, int c1, const int4& g,
-                std::vector<uint64_t>& masks) {
+template <class BoxOf>
+int4 make_table(BoxOf box_of, int c0, int c1, const int4& g, std::vector<uint64_t>& masks) {
   int4 r = make_int4(c0, c1, -1, 0);
   const int m = c1 - c0;
   if (m < kTableMinChildren || m > 64 || g.x >= g.y || g.z >= g.w) return r;
@@ -57,7 +67,7 @@ int4 make_table(const std::vector<int4>& box, int c0, int c1, const int4& g,
   if (off + 2 * S > (size_t)INT32_MAX) return r;
   masks.resize(off + 2 * S, 0);
   for (int c = c0; c < c1; ++c) {
-    const int4 b = box[c];
+    const int4 b = box_of(c);
     if (b.x >= b.y || b.z >= b.w) continue;  // an empty box holds no point
     const uint64_t bit = 1ull << (c - c0);
     const int64_t sx0 = ((int64_t)b.x - g.x) >> shx, sx1 = ((int64_t)b.y - 1 - g.x) >> shx;
@@ -68,6 +78,64 @@ int4 make_table(const std::vector<int4>& box, int c0, int c1, const int4& g,
   r.z = (int)off;
   r.w = logS | (shx << 8) | (shy << 16);
   return r;
+}
+
+// y-slabs of one ring (closed: v[0..m], v[m] = v[0]) with box bx. Only edges
+// whose half-open y-span [min y, max y) overlaps a slab can meet a horizontal
+// line through it, so the crossing test of a point needs only the edges listed
+// for its slab. An edge with equal end heights never takes part and is left
+// out. About three edges per slab; fewer slabs when long edges would repeat
+// too often. Appends to `ent` (offsets out of line when they do not fit in
+// the record) and fills the record's slab fields, with rec.ent relative to
+// the start of `ent`.
+void build_slabs(const int2* v, int64_t m, const int4& bx, std::vector<int4>& ent, LeafRec& rec) {
+  const int64_t ymin = bx.z, height = (int64_t)bx.w - bx.z;
+  int logK = 0;
+  while (logK < 12 && ((int64_t)3 << logK) < m) ++logK;
+  if (height <= 0) logK = 0;
+  std::vector<int64_t> cnt;
+  int sh = 0;
+  int64_t total = 0;
+  for (;; --logK) {
+    const int64_t K = (int64_t)1 << logK;
+    sh = 0;
+    while (height > 0 && (K << sh) < height) ++sh;
+    cnt.assign(K + 1, 0);
+    total = 0;
+    for (int64_t k = 0; k < m; ++k) {
+      const int64_t lo = std::min(v[k].y, v[k + 1].y), hi = std::max(v[k].y, v[k + 1].y);
+      if (lo == hi) continue;
+      const int64_t b0 = (lo - ymin) >> sh, b1 = (hi - 1 - ymin) >> sh;
+      for (int64_t b = b0; b <= b1; ++b) cnt[b + 1]++;
+      total += b1 - b0 + 1;
+    }
+    if (total > 4 * m + 64 && logK > 0) continue;
+    break;
+  }
+  const int64_t K = (int64_t)1 << logK;
+  for (int64_t b = 0; b < K; ++b) cnt[b + 1] += cnt[b];
+  rec.packed = sh | (logK << 8);
+  memset(rec.off, 0, sizeof rec.off);
+  if (K + 1 <= (int64_t)sizeof rec.off && total <= 255) {
+    for (int64_t b = 0; b <= K; ++b) rec.off[b] = (unsigned char)cnt[b];
+  } else {
+    rec.packed |= kLeafExtOff;
+    const int64_t nq = (K + 1 + 3) / 4;
+    const size_t q0 = ent.size();
+    ent.resize(q0 + nq, make_int4(0, 0, 0, 0));
+    uint32_t* o = reinterpret_cast<uint32_t*>(ent.data() + q0);
+    for (int64_t b = 0; b <= K; ++b) o[b] = (uint32_t)cnt[b];
+  }
+  const size_t e0 = ent.size();
+  rec.ent = (long long)e0;
+  ent.resize(e0 + (size_t)total);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t k = 0; k < m; ++k) {
+    const int64_t lo = std::min(v[k].y, v[k + 1].y), hi = std::max(v[k].y, v[k + 1].y);
+    if (lo == hi) continue;
+    const int64_t b0 = (lo - ymin) >> sh, b1 = (hi - 1 - ymin) >> sh;
+    for (int64_t b = b0; b <= b1; ++b) ent[e0 + fill[b]++] = make_int4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
+  }
 }
 
 int build_host(const bm_index_desc* d, HostIndex& h) {
@@ -100,12 +168,15 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
       const int64_t m = d->vert_off[b + 1] - d->vert_off[b];
       if (m < 3)
         return fail(BM_EINVAL, "bm_index_create: ring " + std::to_string(b) + " has fewer than 3 vertices");
+      if (m > (int64_t)1 << 28)
+        return fail(BM_EINVAL, "bm_index_create: ring " + std::to_string(b) + " has more than 2^28 vertices");
     }
     const int64_t V = d->vert_off[B];
     for (int64_t k = 0; k < 2 * V; ++k)
       if (d->verts_xy[k] < 0)
         return fail(BM_ERANGE, "bm_index_create: vertex coordinate outside [0, 2^31-1] at vertex " +
                                    std::to_string(k / 2));
+    h.n_verts = V;
   }
   // parents
   for (int l = 0; l < L; ++l) {
@@ -120,12 +191,15 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   // the new position of its parent
   std::vector<int64_t> base(L + 2, 0);
   for (int l = 0; l <= L; ++l) base[l + 1] = base[l] + size[l];
-  std::vector<std::vector<int32_t>> pos(L + 1);   // pos[l][e] = new position within level
-  std::vector<std::vector<int32_t>> order(L + 1); // order[l][new] = e
+  std::vector<std::vector<int32_t>> pos(L + 1);
+  std::vector<int32_t> leaf_order;  // new leaf position -> caller's block index
   pos[0].resize(size[0]);
-  order[0].resize(size[0]);
-  for (int64_t e = 0; e < size[0]; ++e) pos[0][e] = order[0][e] = (int32_t)e;
-  h.child.assign(base[L], make_int4(0, 0, -1, 0));
+  for (int64_t e = 0; e < size[0]; ++e) pos[0][e] = (int32_t)e;
+  if (L == 0) {
+    leaf_order.resize(B);
+    for (int64_t e = 0; e < B; ++e) leaf_order[e] = (int32_t)e;
+  }
+  h.grp.assign(base[L], GroupRec{kEmptyBox, make_int4(0, 0, -1, 0)});
   h.parent.assign(total_nodes, -1);
   for (int l = 0; l < L; ++l) {
     const int32_t* par = d->parent[l];
@@ -134,72 +208,77 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
     for (int64_t e = 0; e < E; ++e) cnt[pos[l][par[e]] + 1]++;
     for (int64_t g = 0; g < G; ++g) cnt[g + 1] += cnt[g];
     for (int64_t g = 0; g < G; ++g)  // children of the group at new position g
-      h.child[base[l] + g] = make_int4((int)(base[l + 1] + cnt[g]), (int)(base[l + 1] + cnt[g + 1]), -1, 0);
+      h.grp[base[l] + g].child =
+          make_int4((int)(base[l + 1] + cnt[g]), (int)(base[l + 1] + cnt[g + 1]), -1, 0);
     pos[l + 1].resize(E);
-    order[l + 1].resize(E);
+    if (l + 1 == L) leaf_order.resize(E);
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
     for (int64_t e = 0; e < E; ++e) {
       const int64_t np = fill[pos[l][par[e]]]++;
       pos[l + 1][e] = (int32_t)np;
-      order[l + 1][np] = (int32_t)e;
+      if (l + 1 == L) leaf_order[np] = (int32_t)e;
       h.parent[base[l + 1] + np] = (int32_t)(base[l] + pos[l][par[e]]);
     }
   }
 
-  // leaves: rings in new order, each closed by a copy of its first vertex
-  h.box.assign(total_nodes, make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN));
-  h.vert_off.assign(B + 1, 0);
-  h.leaf_id.assign(B, 0);
-  for (int64_t nb = 0; nb < B; ++nb) {
-    const int32_t b = order[L][nb];
-    h.vert_off[nb + 1] = h.vert_off[nb] + (d->vert_off[b + 1] - d->vert_off[b]) + 1;
-    h.leaf_id[nb] = b;
-  }
-  h.verts.resize(h.vert_off[B]);
-  for (int64_t nb = 0; nb < B; ++nb) {
-    const int32_t b = order[L][nb];
-    const int32_t* src = d->verts_xy + 2 * d->vert_off[b];
-    const int64_t m = d->vert_off[b + 1] - d->vert_off[b];
-    int2* dst = h.verts.data() + h.vert_off[nb];
-    int4 bx = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
-    for (int64_t k = 0; k < m; ++k) {
-      const int x = src[2 * k], y = src[2 * k + 1];
-      dst[k] = make_int2(x, y);
-      bx.x = std::min(bx.x, x);
-      bx.y = std::max(bx.y, x);
-      bx.z = std::min(bx.z, y);
-      bx.w = std::max(bx.w, y);
+  // leaves, in parallel over ranges: box, id, y-slab lists
+  h.leaf.assign(B, LeafRec{});
+  const int T = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16,
+                                                              B / 4096 + 1}));
+  std::vector<std::vector<int4>> part(T);
+  auto work = [&](int t) {
+    const int64_t lo = B * t / T, hi = B * (t + 1) / T;
+    std::vector<int2> ring;
+    for (int64_t nb = lo; nb < hi; ++nb) {
+      const int32_t b = leaf_order[nb];
+      const int32_t* src = d->verts_xy + 2 * d->vert_off[b];
+      const int64_t m = d->vert_off[b + 1] - d->vert_off[b];
+      ring.resize(m + 1);
+      int4 bx = kEmptyBox;
+      for (int64_t k = 0; k < m; ++k) {
+        ring[k] = make_int2(src[2 * k], src[2 * k + 1]);
+        grow(bx, make_int4(ring[k].x, ring[k].x, ring[k].y, ring[k].y));
+      }
+      ring[m] = ring[0];
+      LeafRec& rec = h.leaf[nb];
+      rec.box = bx;
+      rec.leaf_id = b;
+      build_slabs(ring.data(), m, bx, part[t], rec);
     }
-    dst[m] = dst[0];
-    h.box[base[L] + nb] = bx;
+  };
+  {
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& x : th) x.join();
   }
+  size_t tot = 0;
+  for (int t = 0; t < T; ++t) tot += part[t].size();
+  h.ent.resize(std::max<size_t>(tot, 1));
+  size_t at = 0;
+  for (int t = 0; t < T; ++t) {
+    const int64_t lo = B * t / T, hi = B * (t + 1) / T;
+    for (int64_t nb = lo; nb < hi; ++nb) h.leaf[nb].ent += (long long)at;
+    if (!part[t].empty()) memcpy(h.ent.data() + at, part[t].data(), part[t].size() * sizeof(int4));
+    at += part[t].size();
+    std::vector<int4>().swap(part[t]);
+  }
+  auto box_of = [&](int64_t c) { return c >= base[L] ? h.leaf[c - base[L]].box : h.grp[c].box; };
   // group boxes, finest group level first
   for (int l = L - 1; l >= 0; --l)
     for (int64_t g = 0; g < size[l]; ++g) {
-      const int4 cr = h.child[base[l] + g];
-      int4 bx = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
-      for (int c = cr.x; c < cr.y; ++c) {
-        const int4 s = h.box[c];
-        bx.x = std::min(bx.x, s.x);
-        bx.y = std::max(bx.y, s.y);
-        bx.z = std::min(bx.z, s.z);
-        bx.w = std::max(bx.w, s.w);
-      }
-      h.box[base[l] + g] = bx;
+      const int4 cr = h.grp[base[l] + g].child;
+      int4 bx = kEmptyBox;
+      for (int c = cr.x; c < cr.y; ++c) grow(bx, box_of(c));
+      h.grp[base[l] + g].box = bx;
     }
   // slot tables: every group, then the virtual root over level 0
   for (int64_t g = 0; g < base[L]; ++g)
-    h.child[g] = make_table(h.box, h.child[g].x, h.child[g].y, h.box[g], h.slot_mask);
-  int4 rb = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
-  for (int64_t e = 0; e < size[0]; ++e) {
-    const int4 s = h.box[e];
-    rb.x = std::min(rb.x, s.x);
-    rb.y = std::max(rb.y, s.y);
-    rb.z = std::min(rb.z, s.z);
-    rb.w = std::max(rb.w, s.w);
-  }
+    h.grp[g].child = make_table(box_of, h.grp[g].child.x, h.grp[g].child.y, h.grp[g].box, h.slot_mask);
+  int4 rb = kEmptyBox;
+  for (int64_t e = 0; e < size[0]; ++e) grow(rb, box_of(e));
   h.root_box = rb;
-  h.root_child = make_table(h.box, 0, (int)size[0], rb, h.slot_mask);
+  h.root_child = make_table(box_of, 0, (int)size[0], rb, h.slot_mask);
   h.n_levels = L;
   h.g0 = (int32_t)size[0];
   h.leaf_base = (int32_t)base[L];
@@ -244,13 +323,11 @@ int make_device(HostIndex& h, bm_index** out) {
   if (e != hipSuccess || ix->num_cu < 1) ix->num_cu = 256;
   KIndex& k = ix->k;
   int rc = BM_OK;
-  if (rc == BM_OK) rc = upload(ix, h.box, &k.box);
-  if (rc == BM_OK) rc = upload(ix, h.child, &k.child);
+  if (rc == BM_OK) rc = upload(ix, h.grp, &k.grp);
+  if (rc == BM_OK) rc = upload(ix, h.leaf, &k.leaf);
+  if (rc == BM_OK) rc = upload(ix, h.ent, &k.ent);
   if (rc == BM_OK) rc = upload(ix, h.slot_mask, reinterpret_cast<const uint64_t**>(&k.slot_mask));
   if (rc == BM_OK) rc = upload(ix, h.parent, &k.parent);
-  if (rc == BM_OK) rc = upload(ix, h.vert_off, &k.vert_off);
-  if (rc == BM_OK) rc = upload(ix, h.leaf_id, &k.leaf_id);
-  if (rc == BM_OK) rc = upload(ix, h.verts, &k.verts);
   if (rc != BM_OK) {
     free_index(ix);
     return rc;
@@ -262,15 +339,16 @@ int make_device(HostIndex& h, bm_index** out) {
   k.leaf_base = h.leaf_base;
   k.n_leaves = h.n_leaves;
   ix->n_blocks = h.n_leaves;
-  ix->n_nodes = (int64_t)h.box.size();
-  ix->n_verts_stored = (int64_t)h.verts.size();
+  ix->n_nodes = (int64_t)h.parent.size();
+  ix->n_verts = h.n_verts;
   ix->n_masks = (int64_t)h.slot_mask.size();
+  ix->n_ent = (int64_t)h.ent.size();
   *out = ix;
   return BM_OK;
 }
 
-// ---- flat file: magic, version, scalars, then the six arrays
-constexpr char kMagic[8] = {'B', 'M', 'I', 'D', 'X', '0', '0', '1'};
+// ---- flat file: magic, scalars, then the arrays
+constexpr char kMagic[8] = {'B', 'M', 'I', 'D', 'X', '0', '0', '2'};
 
 template <class T>
 bool write_vec(FILE* f, const std::vector<T>& v) {
@@ -294,6 +372,70 @@ int download(const T* src, int64_t n, std::vector<T>& v) {
   return e == hipSuccess ? BM_OK : fail(BM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
 }
 
+int write_host(const HostIndex& h, const char* path) {
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(BM_EIO, std::string("cannot open ") + path);
+  const int32_t sc[12] = {h.n_levels, h.g0, h.leaf_base, h.n_leaves,
+                          h.root_child.x, h.root_child.y, h.root_child.z, h.root_child.w,
+                          h.root_box.x, h.root_box.y, h.root_box.z, h.root_box.w};
+  bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(sc, sizeof sc, 1, f) == 1 &&
+            fwrite(&h.n_verts, sizeof h.n_verts, 1, f) == 1 && write_vec(f, h.grp) && write_vec(f, h.leaf) &&
+            write_vec(f, h.ent) && write_vec(f, h.slot_mask) && write_vec(f, h.parent);
+  ok = (fclose(f) == 0) && ok;
+  return ok ? BM_OK : fail(BM_EIO, std::string("write failed on ") + path);
+}
+
+// Structural checks of a loaded index, so that a damaged file cannot send
+// the kernels out of bounds.
+bool consistent(const HostIndex& h) {
+  const int64_t N = (int64_t)h.parent.size(), lb = h.leaf_base, B = h.n_leaves;
+  if (h.n_levels < 0 || h.g0 < 0 || lb < 0 || B < 0 || lb + B != N || (int64_t)h.grp.size() != lb ||
+      (int64_t)h.leaf.size() != B || h.g0 > N || (h.n_levels == 0 ? h.g0 != B : h.g0 > lb))
+    return false;
+  const int64_t NE = (int64_t)h.ent.size();
+  auto table_ok = [&](const int4& c) {
+    if (c.z < 0) return true;
+    const int logS = c.w & 0xff, shx = (c.w >> 8) & 0xff, shy = (c.w >> 16) & 0xff, m = c.y - c.x;
+    if ((logS != 3 && logS != 4) || shx > 31 || shy > 31 || m < 1 || m > 64) return false;
+    const int64_t S = 1 << logS;
+    if ((int64_t)c.z + 2 * S > (int64_t)h.slot_mask.size()) return false;
+    const uint64_t keep = m == 64 ? ~0ull : ((1ull << m) - 1);
+    for (int64_t t = 0; t < 2 * S; ++t)
+      if (h.slot_mask[c.z + t] & ~keep) return false;
+    return true;
+  };
+  for (int64_t g = 0; g < lb; ++g) {
+    const int4 c = h.grp[g].child;
+    if (c.x < 0 || c.x > c.y || c.y > N || c.x <= g || !table_ok(c)) return false;
+  }
+  if (h.root_child.x != 0 || h.root_child.y != h.g0 || !table_ok(h.root_child)) return false;
+  for (int64_t e = 0; e < N; ++e)
+    if (h.parent[e] < -1 || h.parent[e] >= e) return false;
+  for (int64_t b = 0; b < B; ++b) {
+    const LeafRec& r = h.leaf[b];
+    const int sh = r.packed & 0xff, logK = (r.packed >> 8) & 0xff;
+    if (sh > 31 || logK > 12 || (r.packed & ~(0xffff | kLeafExtOff)) != 0) return false;
+    const int64_t K = (int64_t)1 << logK;
+    if (r.box.w > r.box.z && (int64_t)r.box.w - r.box.z > (K << sh)) return false;
+    if (r.ent < 0 || r.ent > NE) return false;
+    std::vector<int64_t> off(K + 1);
+    if (r.packed & kLeafExtOff) {
+      const int64_t nq = (K + 1 + 3) / 4;
+      if (r.ent < nq) return false;
+      const uint32_t* o = reinterpret_cast<const uint32_t*>(h.ent.data() + r.ent - nq);
+      for (int64_t j = 0; j <= K; ++j) off[j] = o[j];
+    } else {
+      if (K + 1 > (int64_t)sizeof r.off) return false;
+      for (int64_t j = 0; j <= K; ++j) off[j] = r.off[j];
+    }
+    if (off[0] != 0) return false;
+    for (int64_t j = 0; j < K; ++j)
+      if (off[j] > off[j + 1]) return false;
+    if (r.ent + off[K] > NE) return false;
+  }
+  return true;
+}
+
 }  // namespace
 
 int index_create(const bm_index_desc* d, bm_index** out) {
@@ -312,25 +454,28 @@ int index_save(const bm_index* ix, const char* path) {
   HostIndex h;
   const KIndex& k = ix->k;
   int rc = BM_OK;
-  if (rc == BM_OK) rc = download(k.box, ix->n_nodes, h.box);
-  if (rc == BM_OK) rc = download(k.child, (int64_t)k.leaf_base, h.child);
+  if (rc == BM_OK) rc = download(k.grp, (int64_t)k.leaf_base, h.grp);
+  if (rc == BM_OK) rc = download(k.leaf, (int64_t)k.n_leaves, h.leaf);
+  if (rc == BM_OK) rc = download(k.ent, ix->n_ent, h.ent);
   if (rc == BM_OK) rc = download(reinterpret_cast<const uint64_t*>(k.slot_mask), ix->n_masks, h.slot_mask);
   if (rc == BM_OK) rc = download(k.parent, ix->n_nodes, h.parent);
-  if (rc == BM_OK) rc = download(k.vert_off, (int64_t)k.n_leaves + 1, h.vert_off);
-  if (rc == BM_OK) rc = download(k.leaf_id, (int64_t)k.n_leaves, h.leaf_id);
-  if (rc == BM_OK) rc = download(k.verts, ix->n_verts_stored, h.verts);
   if (rc != BM_OK) return rc;
-  FILE* f = fopen(path, "wb");
-  if (!f) return fail(BM_EIO, std::string("bm_index_save: cannot open ") + path);
-  const int32_t sc[12] = {k.n_levels, k.g0, k.leaf_base, k.n_leaves,
-                          k.root_child.x, k.root_child.y, k.root_child.z, k.root_child.w,
-                          k.root_box.x, k.root_box.y, k.root_box.z, k.root_box.w};
-  bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(sc, sizeof sc, 1, f) == 1 && write_vec(f, h.box) &&
-            write_vec(f, h.child) && write_vec(f, h.slot_mask) && write_vec(f, h.parent) &&
-            write_vec(f, h.vert_off) &&
-            write_vec(f, h.leaf_id) && write_vec(f, h.verts);
-  ok = (fclose(f) == 0) && ok;
-  return ok ? BM_OK : fail(BM_EIO, std::string("bm_index_save: write failed on ") + path);
+  h.n_levels = k.n_levels;
+  h.g0 = k.g0;
+  h.leaf_base = k.leaf_base;
+  h.n_leaves = k.n_leaves;
+  h.root_child = k.root_child;
+  h.root_box = k.root_box;
+  h.n_verts = ix->n_verts;
+  return write_host(h, path);
+}
+
+int index_build_file(const bm_index_desc* d, const char* path) {
+  if (!path) return fail(BM_EINVAL, "bm_index_build_file: null path");
+  HostIndex h;
+  int rc = build_host(d, h);
+  if (rc != BM_OK) return rc;
+  return write_host(h, path);
 }
 
 int index_load(const char* path, bm_index** out) {
@@ -341,11 +486,11 @@ int index_load(const char* path, bm_index** out) {
   HostIndex h;
   char magic[8];
   int32_t sc[12];
-  const int64_t lim = (int64_t)1 << 40;
+  const int64_t lim = (int64_t)1 << 36;
   bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMagic, 8) == 0 && fread(sc, sizeof sc, 1, f) == 1 &&
-            read_vec(f, h.box, INT32_MAX) && read_vec(f, h.child, INT32_MAX) &&
-            read_vec(f, h.slot_mask, INT32_MAX) && read_vec(f, h.parent, INT32_MAX) &&
-            read_vec(f, h.vert_off, INT32_MAX) && read_vec(f, h.leaf_id, INT32_MAX) && read_vec(f, h.verts, lim);
+            fread(&h.n_verts, sizeof h.n_verts, 1, f) == 1 && read_vec(f, h.grp, INT32_MAX) &&
+            read_vec(f, h.leaf, INT32_MAX) && read_vec(f, h.ent, lim) && read_vec(f, h.slot_mask, INT32_MAX) &&
+            read_vec(f, h.parent, INT32_MAX);
   fclose(f);
   if (!ok) return fail(BM_EIO, std::string("bm_index_load: malformed file ") + path);
   h.n_levels = sc[0];
@@ -354,34 +499,7 @@ int index_load(const char* path, bm_index** out) {
   h.n_leaves = sc[3];
   h.root_child = make_int4(sc[4], sc[5], sc[6], sc[7]);
   h.root_box = make_int4(sc[8], sc[9], sc[10], sc[11]);
-  // structural checks so that a damaged file cannot send the kernels out of bounds
-  const int64_t N = (int64_t)h.box.size();
-  bool good = h.n_levels >= 0 && h.g0 >= 0 && h.leaf_base >= 0 && h.n_leaves >= 0 &&
-              (int64_t)h.leaf_base + h.n_leaves == N && (int64_t)h.child.size() == h.leaf_base &&
-              (int64_t)h.parent.size() == N && (int64_t)h.vert_off.size() == (int64_t)h.n_leaves + 1 &&
-              (int64_t)h.leaf_id.size() == h.n_leaves && h.g0 <= N && (h.n_levels > 0 || h.g0 == h.n_leaves) &&
-              (h.n_levels == 0 || h.g0 <= h.leaf_base);
-  if (good && !h.vert_off.empty()) {
-    good = h.vert_off[0] == 0 && h.vert_off.back() == (int64_t)h.verts.size();
-    for (int64_t b = 0; good && b < h.n_leaves; ++b) good = h.vert_off[b + 1] - h.vert_off[b] >= 2;
-  }
-  auto table_ok = [&](const int4& c) {
-    if (c.z < 0) return true;
-    const int logS = c.w & 0xff, shx = (c.w >> 8) & 0xff, shy = (c.w >> 16) & 0xff, m = c.y - c.x;
-    if ((logS != 3 && logS != 4) || shx > 31 || shy > 31 || m < 1 || m > 64) return false;
-    const int64_t S = 1 << logS;
-    if ((int64_t)c.z + 2 * S > (int64_t)h.slot_mask.size()) return false;
-    const uint64_t keep = m == 64 ? ~0ull : ((1ull << m) - 1);
-    for (int64_t t = 0; t < 2 * S; ++t)
-      if (h.slot_mask[c.z + t] & ~keep) return false;
-    return true;
-  };
-  for (int64_t g = 0; good && g < h.leaf_base; ++g)
-    good = h.child[g].x >= 0 && h.child[g].x <= h.child[g].y && h.child[g].y <= N && h.child[g].x > g &&
-           table_ok(h.child[g]);
-  good = good && h.root_child.x == 0 && h.root_child.y == h.g0 && table_ok(h.root_child);
-  for (int64_t e = 0; good && e < N; ++e) good = h.parent[e] >= -1 && h.parent[e] < N && h.parent[e] < e;
-  if (!good) return fail(BM_EIO, std::string("bm_index_load: inconsistent index in ") + path);
+  if (!consistent(h)) return fail(BM_EIO, std::string("bm_index_load: inconsistent index in ") + path);
   return make_device(h, out);
 }
 

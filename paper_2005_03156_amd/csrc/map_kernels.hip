@@ -38,7 +38,7 @@ struct WaveLds {
   unsigned node[2][kCap];
   unsigned char lane[2][kCap];
   unsigned char ovf[kWave];
-  unsigned long long ch_j0[kCapChunk];  // first ring vertex of a chunk
+  unsigned long long ch_j0[kCapChunk];  // first entry of a chunk in `ent`
   unsigned char ch_q[kCapChunk];        // pair (within the round) of a chunk
   unsigned char ch_n[kCapChunk];        // edges in the chunk
 };
@@ -90,15 +90,41 @@ __device__ __forceinline__ unsigned crosses(int2 a, int2 b, int2 p) {
   return r;
 }
 
-// Full crossing-number test of one ring (stored closed).
-__device__ unsigned ring_parity(const KIndex& ix, int leaf, int2 p) {
-  const long long v0 = ix.vert_off[leaf], v1 = ix.vert_off[leaf + 1] - 1;
+__device__ __forceinline__ int4 node_box(const KIndex& ix, int e) {
+  return e >= ix.leaf_base ? ix.leaf[e - ix.leaf_base].box : ix.grp[e].box;
+}
+
+// The slab of leaf record r holding height py (which lies in the leaf's
+// y-extent) as a range [first, end) of `ent`.
+__device__ __forceinline__ void slab_range(const KIndex& ix, const LeafRec& r, const int leaf, const int py,
+                                           long long& first, unsigned& len) {
+  const int sh = r.packed & 0xff, logK = (r.packed >> 8) & 0xff;
+  const int b = (int)(((long long)py - r.box.z) >> sh);
+  unsigned o0, o1;
+  if (r.packed & kLeafExtOff) {
+    const long long nq = ((1ll << logK) + 1 + 3) >> 2;
+    const unsigned* o = reinterpret_cast<const unsigned*>(ix.ent + r.ent - nq);
+    o0 = o[b];
+    o1 = o[b + 1];
+  } else {
+    const unsigned char* o = ix.leaf[leaf].off;
+    o0 = o[b];
+    o1 = o[b + 1];
+  }
+  first = r.ent + o0;
+  len = o1 - o0;
+}
+
+// Crossing parity of a point against one leaf (point inside the leaf box).
+__device__ unsigned leaf_parity(const KIndex& ix, int leaf, int2 p) {
+  const LeafRec r = ix.leaf[leaf];
+  long long first;
+  unsigned len;
+  slab_range(ix, r, leaf, p.y, first, len);
   unsigned acc = 0;
-  int2 a = ix.verts[v0];
-  for (long long j = v0; j < v1; ++j) {
-    const int2 b = ix.verts[j + 1];
-    acc ^= crosses(a, b, p);
-    a = b;
+  for (unsigned j = 0; j < len; ++j) {
+    const int4 e = ix.ent[first + j];
+    acc ^= crosses(make_int2(e.x, e.y), make_int2(e.z, e.w), p);
   }
   return acc;
 }
@@ -114,16 +140,16 @@ __device__ unsigned walk_point(const KIndex& ix, int2 p) {
       if (par < 0) break;
       e = par + 1;
       par = ix.parent[par];
-      end = par < 0 ? ix.g0 : ix.child[par].y;
+      end = par < 0 ? ix.g0 : ix.grp[par].child.y;
       continue;
     }
-    if (in_box(ix.box[e], p)) {
+    if (in_box(node_box(ix, e), p)) {
       if (e >= ix.leaf_base) {
         const int leaf = e - ix.leaf_base;
-        if (ring_parity(ix, leaf, p)) best = min(best, (unsigned)ix.leaf_id[leaf]);
+        if (leaf_parity(ix, leaf, p)) best = min(best, (unsigned)ix.leaf[leaf].leaf_id);
         ++e;
       } else {
-        const int4 c = ix.child[e];
+        const int4 c = ix.grp[e].child;
         par = e;
         e = c.x;
         end = c.y;
@@ -161,7 +187,7 @@ __device__ __forceinline__ void emit(WaveLds& S, int dst, bool pred, unsigned no
 // Called with all 64 lanes active; `has` masks lanes without an item.
 __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
                                        const int4 gb, const int2 pp, int pl, int dst,
-                                       unsigned& cnt) {
+                                       unsigned& cnt, const bool leaves) {
   const int m = has ? ci.y - ci.x : 0;
   for (int base = 0; wave_any(base < m); base += 64) {
     unsigned long long cand = 0ull;
@@ -188,8 +214,13 @@ __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, c
       const int b2 = h2 ? __builtin_ctzll(cand) : 0;
       cand &= cand - 1ull;
       int4 bx1 = make_int4(0, 0, 0, 0), bx2 = make_int4(0, 0, 0, 0);
-      if (h1) bx1 = ix.box[c0 + b1];
-      if (h2) bx2 = ix.box[c0 + b2];
+      if (leaves) {
+        if (h1) bx1 = ix.leaf[c0 + b1 - ix.leaf_base].box;
+        if (h2) bx2 = ix.leaf[c0 + b2 - ix.leaf_base].box;
+      } else {
+        if (h1) bx1 = ix.grp[c0 + b1].box;
+        if (h2) bx2 = ix.grp[c0 + b2].box;
+      }
       emit(S, dst, h1 && in_box(bx1, pp), (unsigned)(c0 + b1), pl, cnt);
       emit(S, dst, h2 && in_box(bx2, pp), (unsigned)(c0 + b2), pl, cnt);
     }
@@ -213,7 +244,7 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
   // ---- the root's children (level 0), one item per point
   int cur = 0;
   unsigned cnt = 0;
-  expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt);
+  expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt, ix.n_levels == 0);
   cnt = min(cnt, (unsigned)kCap);
   wave_sync();
 
@@ -228,31 +259,34 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
       const int pl = has ? S.lane[cur][q] : 0;
       int4 ci = make_int4(0, 0, -1, 0), gb = make_int4(0, 0, 0, 0);
       if (has) {
-        ci = ix.child[node];
-        gb = ix.box[node];
+        ci = ix.grp[node].child;
+        gb = ix.grp[node].box;
       }
-      expand(ix, S, has, ci, gb, S.pts[pl], pl, nxt, ncnt);
+      expand(ix, S, has, ci, gb, S.pts[pl], pl, nxt, ncnt, l + 1 == ix.n_levels);
     }
     cnt = min(ncnt, (unsigned)kCap);
     cur = nxt;
     wave_sync();
   }
 
-  // ---- crossing-number test on the (leaf, point) pairs of list `cur`,
-  // 64 pairs per round; each pair's ring edges are cut into chunks of
-  // kChunk edges and all chunks of the round are dealt across the lanes.
+  // ---- crossing-number test on the (leaf, point) pairs of list `cur`, 64
+  // pairs per round. A pair only needs the ring edges listed for the y-slab
+  // holding its point (the pair passed the leaf's box test, so the point lies
+  // in the ring's y-extent); that list is cut into chunks of kChunk edges and
+  // all chunks of the round are dealt across the lanes.
   for (unsigned r = 0; r < cnt; r += kWave) {
     const unsigned q = r + lane;
     const bool has = q < cnt;
-    long long v0 = 0, v1 = 0;
-    unsigned bid = 0;
+    long long l0 = 0;
+    unsigned len = 0, bid = 0;
     if (has) {
       const int leaf = (int)S.node[cur][q] - ix.leaf_base;
-      v0 = ix.vert_off[leaf];
-      v1 = ix.vert_off[leaf + 1] - 1;  // index of the closing copy
-      bid = (unsigned)ix.leaf_id[leaf];
+      const int2 pp = S.pts[S.lane[cur][q]];
+      const LeafRec rec = ix.leaf[leaf];
+      bid = (unsigned)rec.leaf_id;
+      slab_range(ix, rec, leaf, pp.y, l0, len);
     }
-    const unsigned long long nch = has ? (unsigned long long)((v1 - v0 + kChunk - 1) >> kChunkShift) : 0ull;
+    const unsigned long long nch = (len + kChunk - 1) >> kChunkShift;
     const unsigned long long incl = wave_incl_scan(nch, lane);
     const unsigned long long start = incl - nch;
     const unsigned long long total = __shfl(incl, kWave - 1);
@@ -260,10 +294,10 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
     for (unsigned long long w = 0; w < total; w += kCapChunk) {
       const unsigned long long a = max(start, w), b = min(start + nch, w + (unsigned long long)kCapChunk);
       for (unsigned long long c = a; c < b; ++c) {
-        const long long j0 = v0 + (long long)((c - start) << kChunkShift);
-        S.ch_j0[c - w] = (unsigned long long)j0;
+        const unsigned k0 = (unsigned)((c - start) << kChunkShift);
+        S.ch_j0[c - w] = (unsigned long long)(l0 + k0);
         S.ch_q[c - w] = (unsigned char)lane;
-        S.ch_n[c - w] = (unsigned char)min((long long)kChunk, v1 - j0);
+        S.ch_n[c - w] = (unsigned char)min((unsigned)kChunk, len - k0);
       }
       wave_sync();
       const unsigned nw = (unsigned)min((unsigned long long)kCapChunk, total - w);
@@ -271,13 +305,14 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
         const long long j0 = (long long)S.ch_j0[c];
         const int ne = S.ch_n[c];
         const unsigned pq = S.ch_q[c];
-        int2 v[kChunk + 1];
+        int4 ev[kChunk];
 #pragma unroll
-        for (int u = 0; u <= kChunk; ++u) v[u] = (u <= ne) ? ix.verts[j0 + u] : make_int2(0, 0);
+        for (int u = 0; u < kChunk; ++u) ev[u] = (u < ne) ? ix.ent[j0 + u] : make_int4(0, 0, 0, 0);
         const int2 pp = S.pts[S.lane[cur][r + pq]];
         unsigned acc = 0;
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) acc ^= (u < ne) ? crosses(v[u], v[u + 1], pp) : 0u;
+        for (int u = 0; u < kChunk; ++u)
+          acc ^= (u < ne) ? crosses(make_int2(ev[u].x, ev[u].y), make_int2(ev[u].z, ev[u].w), pp) : 0u;
         if (acc) atomicXor(&S.par[pq], 1u);
       }
       wave_sync();

@@ -1,0 +1,166 @@
+"""The host-side index builder without a GPU: the file written by
+bm_index_build_file is parsed here and its derived structures are checked
+against their definitions (half-open boxes, unions, children ranges, slot
+tables as supersets, y-slab edge lists as supersets of the straddling
+edges)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+GROUP = np.dtype([("box", np.int32, 4), ("child", np.int32, 4)])
+LEAF = np.dtype([("box", np.int32, 4), ("ent", np.int64), ("leaf_id", np.int32), ("packed", np.int32),
+                 ("off", np.uint8, 32)])
+EXT = 1 << 24
+
+
+def read_index(path):
+    with open(path, "rb") as f:
+        buf = f.read()
+    assert buf[:8] == b"BMIDX002"
+    sc = np.frombuffer(buf, np.int32, 12, 8)
+    pos = 8 + 48 + 8
+    out = {"n_verts": int(np.frombuffer(buf, np.int64, 1, 56)[0])}
+    for name, dt, w in [("grp", GROUP, 1), ("leaf", LEAF, 1), ("ent", np.int32, 4), ("slot_mask", np.uint64, 1),
+                        ("parent", np.int32, 1)]:
+        n = int(np.frombuffer(buf, np.int64, 1, pos)[0])
+        pos += 8
+        a = np.frombuffer(buf, dt, n * w, pos)
+        pos += a.nbytes
+        out[name] = a.reshape(n, w) if w > 1 else a
+    assert pos == len(buf)
+    out.update(n_levels=int(sc[0]), g0=int(sc[1]), leaf_base=int(sc[2]), n_leaves=int(sc[3]),
+               root_child=sc[4:8].copy(), root_box=sc[8:12].copy())
+    lb = out["leaf_base"]
+    out["box"] = np.concatenate([out["grp"]["box"], out["leaf"]["box"]]) if lb else out["leaf"]["box"]
+    out["child"] = out["grp"]["child"]
+    return out
+
+
+def slab_of(ix, nb, py):
+    """Entries (a.x, a.y, b.x, b.y) listed for height py in leaf nb."""
+    r = ix["leaf"][nb]
+    sh, logK = int(r["packed"]) & 0xFF, (int(r["packed"]) >> 8) & 0xFF
+    K = 1 << logK
+    s = (int(py) - int(r["box"][2])) >> sh
+    assert 0 <= s < K
+    if int(r["packed"]) & EXT:
+        nq = (K + 1 + 3) // 4
+        offs = ix["ent"][int(r["ent"]) - nq:int(r["ent"])].ravel().view(np.uint32)[:K + 1]
+    else:
+        offs = r["off"][:K + 1]
+    e0 = int(r["ent"])
+    return ix["ent"][e0 + int(offs[s]):e0 + int(offs[s + 1])]
+
+
+@pytest.fixture(scope="module")
+def cfg2_index(tmp_path_factory):
+    import paper_2005_03156_amd as bm
+    g = synth.geometry(2)
+    p = str(tmp_path_factory.mktemp("idx") / "c2.bmi")
+    bm.build_index_file(p, g.vert_off, g.verts, g.n_groups, g.parents)
+    return g, read_index(p)
+
+
+def test_structure_and_boxes(cfg2_index):
+    g, ix = cfg2_index
+    B, lb = ix["n_leaves"], ix["leaf_base"]
+    assert B == g.n_blocks and lb == sum(g.n_groups) and ix["g0"] == g.n_groups[0]
+    assert ix["n_verts"] == g.verts.shape[0]
+    # leaf ids are a permutation; leaf boxes are the ring extents (oracle's own)
+    lid = ix["leaf"]["leaf_id"]
+    assert np.array_equal(np.sort(lid), np.arange(B))
+    want = oracle.ring_boxes(g.vert_off, g.verts)[lid]
+    assert np.array_equal(ix["leaf"]["box"], want)
+    # children ranges are contiguous, consecutive and consistent with parents
+    child = ix["child"]
+    for gnode in np.random.default_rng(1).choice(lb, 300, replace=False):
+        c0, c1 = child[gnode, 0], child[gnode, 1]
+        assert np.all(ix["parent"][c0:c1] == gnode)
+        # group box = smallest box holding the children's boxes
+        cb = ix["box"][c0:c1]
+        assert np.array_equal(ix["box"][gnode], [cb[:, 0].min(), cb[:, 1].max(), cb[:, 2].min(), cb[:, 3].max()])
+    # every level's children ranges tile the next level in order
+    starts = child[:, 0]
+    assert np.all(starts[1:] >= starts[:-1])
+
+
+def _table_candidates(ix, crec, gbox, px, py):
+    c0, c1, off, packed = (int(v) for v in crec)
+    logS, shx, shy = packed & 0xFF, (packed >> 8) & 0xFF, (packed >> 16) & 0xFF
+    S = 1 << logS
+    sx, sy = (px - int(gbox[0])) >> shx, (py - int(gbox[2])) >> shy
+    if not (0 <= sx < S and 0 <= sy < S):
+        return 0
+    return int(ix["slot_mask"][off + sx]) & int(ix["slot_mask"][off + S + sy])
+
+
+def test_slot_tables_are_supersets(cfg2_index):
+    g, ix = cfg2_index
+    rng = np.random.default_rng(2)
+    groups = [(ix["root_child"], ix["root_box"])]
+    tabbed = np.flatnonzero(ix["child"][:, 2] >= 0)
+    assert tabbed.size > 3000  # regions and counties carry tables
+    groups += [(ix["child"][k], ix["box"][k]) for k in rng.choice(tabbed, 400, replace=False)]
+    for crec, gb in groups:
+        c0, c1 = int(crec[0]), int(crec[1])
+        assert int(crec[2]) >= 0
+        for _ in range(40):
+            px = int(rng.integers(gb[0], gb[1]))
+            py = int(rng.integers(gb[2], gb[3]))
+            cand = _table_candidates(ix, crec, gb, px, py)
+            cb = ix["box"][c0:c1]
+            inside = (cb[:, 0] <= px) & (px < cb[:, 1]) & (cb[:, 2] <= py) & (py < cb[:, 3])
+            for k in np.flatnonzero(inside):
+                assert cand >> int(k) & 1
+            assert cand >> (c1 - c0) == 0
+
+
+def test_y_slabs_list_every_straddling_edge(cfg2_index):
+    """For any height in a leaf's y-extent, its slab lists (as vertex pairs)
+    every edge of the caller's ring that straddles that height, and only
+    edges of that ring."""
+    g, ix = cfg2_index
+    rng = np.random.default_rng(3)
+    for nb in rng.choice(ix["n_leaves"], 300, replace=False):
+        b = int(ix["leaf"]["leaf_id"][nb])
+        ring = g.verts[g.vert_off[b]:g.vert_off[b + 1]].astype(np.int64)
+        a, c = ring, np.roll(ring, -1, axis=0)
+        edges = {tuple(e) for e in np.concatenate([a, c], 1).tolist()}
+        box = ix["leaf"]["box"][nb]
+        for py in list(rng.integers(box[2], box[3], 20)) + [int(box[2]), int(box[3]) - 1]:
+            listed = slab_of(ix, nb, py)
+            lset = {tuple(e) for e in listed.tolist()}
+            assert lset <= edges
+            strad = np.flatnonzero((a[:, 1] > py) != (c[:, 1] > py))
+            for k in strad:
+                assert (a[k, 0], a[k, 1], c[k, 0], c[k, 1]) in lset
+            assert len(listed) <= len(ring)
+
+
+def test_y_slab_parity_equals_oracle(cfg2_index):
+    """Crossing parity over the listed slab edges only (intersections computed
+    with exact rationals) equals the oracle's parity over the full ring."""
+    from fractions import Fraction
+    g, ix = cfg2_index
+    rng = np.random.default_rng(4)
+    for nb in rng.choice(ix["n_leaves"], 60, replace=False):
+        b = int(ix["leaf"]["leaf_id"][nb])
+        ring = g.verts[g.vert_off[b]:g.vert_off[b + 1]]
+        box = ix["leaf"]["box"][nb]
+        for _ in range(10):
+            px, py = int(rng.integers(box[0], box[1])), int(rng.integers(box[2], box[3]))
+            cnt = 0
+            for ax, ay, bx, by in slab_of(ix, nb, py).tolist():
+                if (ay > py) != (by > py) and Fraction(ax) + Fraction((py - ay) * (bx - ax), by - ay) > px:
+                    cnt += 1
+            assert (cnt & 1) == int(oracle.inside(ring, px, py))
+
+
+def test_build_file_rejects_bad_input(tmp_path):
+    import paper_2005_03156_amd as bm
+    with pytest.raises(bm.BlockmapError) as e:
+        bm.build_index_file(str(tmp_path / "x.bmi"), [0, 3], [[0, 0], [5, -2], [0, 5]])
+    assert e.value.code == bm.BM_ERANGE
