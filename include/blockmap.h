@@ -134,7 +134,8 @@ int bm_index_build_file(const bm_index_desc* desc, const char* path);
  * Asynchronous: results are ready when the stream reaches this point. The
  * index must live on the current device. n == 0 is a no-op. xy and out_ids
  * must not overlap. The index is read-only, so calls on different streams may
- * run at the same time. Uses no memory beyond its arguments.
+ * run at the same time. Calls of 2^20 points or more use stream-ordered
+ * scratch for the spatial pre-sort (see bm_tuning.presort).
  * Errors: BM_EINVAL (null index, n < 0, null buffers when n > 0, index on
  * another device), BM_EHIP (launch failure). */
 int map_points(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
@@ -157,6 +158,10 @@ typedef struct {
   int32_t edge_chunk;       /* ring edges per crossing-test work item: 4, 8 or 16 */
   int32_t blocks_per_cu;    /* resident workgroups per compute unit (1..8) */
   int32_t tile_points;      /* batched form: points per unit of work (multiple of 64, <= 2^20) */
+  int32_t presort;          /* 1: a call of at least 2^20 points is first counting-sorted by a
+                               spatial key (a 64 x 64 Morton grid over the index), 2^22 points
+                               at a time, so that nearby points are mapped together; it uses
+                               48 MB of stream-ordered device scratch (hipMallocAsync). 0: off */
 } bm_tuning;
 
 /* Out-of-range fields are replaced by their defaults. */

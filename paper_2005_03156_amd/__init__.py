@@ -46,7 +46,8 @@ class IndexInfo(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("edge_chunk", C.c_int32), ("blocks_per_cu", C.c_int32), ("tile_points", C.c_int32)]
+    _fields_ = [("edge_chunk", C.c_int32), ("blocks_per_cu", C.c_int32), ("tile_points", C.c_int32),
+                ("presort", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -29,8 +29,9 @@ void clear_error() { g_err.clear(); }
 const char* error_text() { return g_err.c_str(); }
 
 Tuning tuning_from(const bm_tuning* t) {
-  Tuning r{4, 5, 2048};
+  Tuning r{4, 5, 2048, 1};
   if (t) {
+    if (t->presort == 0 || t->presort == 1) r.presort = t->presort;
     if (t->edge_chunk == 4 || t->edge_chunk == 8 || t->edge_chunk == 16) r.edge_chunk = t->edge_chunk;
     if (t->blocks_per_cu >= 1 && t->blocks_per_cu <= 8) r.blocks_per_cu = t->blocks_per_cu;
     if (t->tile_points >= 64 && t->tile_points <= (1 << 20) && t->tile_points % 64 == 0)
@@ -123,6 +124,7 @@ __attribute__((visibility("default"))) int bm_tuning_default(bm_tuning* t) {
   t->edge_chunk = d.edge_chunk;
   t->blocks_per_cu = d.blocks_per_cu;
   t->tile_points = d.tile_points;
+  t->presort = d.presort;
   return BM_OK;
 }
 

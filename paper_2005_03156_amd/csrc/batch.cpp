@@ -212,14 +212,15 @@ __attribute__((visibility("default"))) int bm_autotune(const bm_index* index, co
       char line[512];
       while (fgets(line, sizeof line, f)) {
         char k2[256];
-        int a, b, c;
-        if (sscanf(line, "%255s %d %d %d", k2, &a, &b, &c) == 4 && strcmp(k2, key) == 0) {
+        int a, b, c, d;
+        if (sscanf(line, "%255s %d %d %d %d", k2, &a, &b, &c, &d) == 5 && strcmp(k2, key) == 0) {
           fclose(f);
-          bm_tuning t{a, b, c};
+          bm_tuning t{a, b, c, d};
           const Tuning v = tuning_from(&t);
           out->edge_chunk = v.edge_chunk;
           out->blocks_per_cu = v.blocks_per_cu;
           out->tile_points = v.tile_points;
+          out->presort = v.presort;
           return BM_OK;
         }
       }
@@ -270,12 +271,19 @@ __attribute__((visibility("default"))) int bm_autotune(const bm_index* index, co
     const int bpcs[4] = {3, 4, 5, 6};
     for (int c : chunks)
       for (int b : bpcs) {
-        Tuning t{c, b, best.tile_points};
+        Tuning t{c, b, best.tile_points, 1};
         float ms = 0;
         e = time_it(t, false, &ms);
         if (e != hipSuccess) break;
         if (ms < best_ms) { best_ms = ms; best = t; }
       }
+    if (e == hipSuccess && n >= kPresortMin) {  // is the spatial pre-sort worth it here?
+      Tuning t = best;
+      t.presort = 0;
+      float ms = 0;
+      e = time_it(t, false, &ms);
+      if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = t; }
+    }
     if (e == hipSuccess) {
       const int units[3] = {512, 2048, 8192};
       float bu = 1e30f;
@@ -299,8 +307,9 @@ __attribute__((visibility("default"))) int bm_autotune(const bm_index* index, co
     out->edge_chunk = best.edge_chunk;
     out->blocks_per_cu = best.blocks_per_cu;
     out->tile_points = best.tile_points;
+    out->presort = best.presort;
     if (FILE* f = fopen(path.c_str(), "a")) {
-      fprintf(f, "%s %d %d %d\n", key, best.edge_chunk, best.blocks_per_cu, best.tile_points);
+      fprintf(f, "%s %d %d %d %d\n", key, best.edge_chunk, best.blocks_per_cu, best.tile_points, best.presort);
       fclose(f);
     }
     return BM_OK;

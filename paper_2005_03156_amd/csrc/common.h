@@ -58,10 +58,16 @@ struct BatchEntry {
   int64_t n;
 };
 
+// Calls of at least kPresortMin points are spatially sorted in chunks of
+// kPresortChunk points before mapping (when Tuning::presort is set).
+constexpr long long kPresortMin = 1 << 20;
+constexpr long long kPresortChunk = 1 << 22;
+
 struct Tuning {
   int edge_chunk;     // 4, 8 or 16
   int blocks_per_cu;  // 1..8
   int tile_points;    // batched form: points per unit of work taken from the counter (multiple of 64)
+  int presort;        // 0 / 1: spatial sort of large calls (uses stream-ordered scratch)
 };
 
 Tuning tuning_from(const bm_tuning* t);

@@ -232,7 +232,7 @@ __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, c
 template <int kChunkShift>
 __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int lane,
                                          const int2* __restrict__ xy, const int nvalid,
-                                         int* __restrict__ out) {
+                                         int* __restrict__ out, const int* __restrict__ perm = nullptr) {
   constexpr int kChunk = 1 << kChunkShift;
   const bool valid = lane < nvalid;
   const int2 p = valid ? xy[lane] : make_int2(0, 0);
@@ -323,7 +323,7 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
 
   unsigned best = S.best[lane];
   if (valid && S.ovf[lane]) best = min(best, walk_point(ix, p));
-  if (valid) out[lane] = (int)best;
+  if (valid) out[perm ? perm[lane] : lane] = (int)best;
   wave_sync();
 }
 
@@ -411,6 +411,123 @@ __global__ __launch_bounds__(kBlock) void batch_map_kernel(const KIndex ix, cons
   }
 }
 
+// ---- spatial binning ------------------------------------------------------
+// Points arrive in any order; a wave maps 64 of them together, and its tree
+// nodes, slab lists and cache lines are shared only when those points are
+// close. Before mapping, each chunk of points is therefore counting-sorted by
+// a 12-bit key: the Morton index of its cell in a 64 x 64 grid over the root
+// box (points outside fall in the nearest border cell). The mapping kernel
+// then reads the sorted copy and writes each result back to the point's
+// original position. Each point's result depends on that point alone, so the
+// order does not change any output.
+constexpr int kBinBits = 6;  // per axis
+constexpr int kBins = 1 << (2 * kBinBits);
+constexpr int kBinBlocks = 256;  // blocks of the count and scatter passes
+
+__device__ __forceinline__ unsigned spread6(unsigned v) {
+  v &= 63u;
+  v = (v | (v << 4)) & 0x0F0Fu;
+  v = (v | (v << 2)) & 0x3333u;
+  v = (v | (v << 1)) & 0x5555u;
+  return v;
+}
+
+__device__ __forceinline__ unsigned bin_of(const int2 p, const int4 rb, const int shx, const int shy) {
+  const long long dx = (long long)p.x - rb.x, dy = (long long)p.y - rb.z;
+  const long long top = (1 << kBinBits) - 1;
+  const unsigned cx = (unsigned)min(top, max(0ll, dx >> shx));
+  const unsigned cy = (unsigned)min(top, max(0ll, dy >> shy));
+  return spread6(cx) | (spread6(cy) << 1);
+}
+
+// Each block counts the bins of its range of the chunk in LDS and adds the
+// counts to the chunk's per-bin totals.
+__global__ __launch_bounds__(1024) void bin_count_kernel(const int2* __restrict__ xy, const long long n,
+                                                         const long long per, const int4 rb, const int shx,
+                                                         const int shy, unsigned* __restrict__ tot) {
+  __shared__ unsigned h[kBins];
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[bin_of(xy[i], rb, shx, shy)], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&tot[i], h[i]);
+}
+
+// cursor[bin] = first sorted position of the bin (exclusive scan of tot);
+// tot is cleared for the next chunk. One block.
+__global__ __launch_bounds__(1024) void bin_scan_kernel(unsigned* __restrict__ tot, unsigned* __restrict__ cursor) {
+  constexpr int kPer = kBins / 1024;
+  __shared__ unsigned part[1024];
+  unsigned v[kPer], mine = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    v[k] = tot[threadIdx.x * kPer + k];
+    mine += v[k];
+  }
+  part[threadIdx.x] = mine;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const unsigned t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  unsigned run = part[threadIdx.x] - mine;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    cursor[threadIdx.x * kPer + k] = run;
+    tot[threadIdx.x * kPer + k] = 0;
+    run += v[k];
+  }
+}
+
+__global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ tot) {
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) tot[i] = 0;
+}
+
+// Each block recounts its range, reserves a run of every bin it uses from the
+// bin cursors, and scatters its points into those runs: sorted[pos] = point,
+// perm[pos] = its index in the chunk. (The order inside a bin varies from run
+// to run; no output depends on it.)
+__global__ __launch_bounds__(1024) void bin_scatter_kernel(const int2* __restrict__ xy, const long long n,
+                                                           const long long per, const int4 rb, const int shx,
+                                                           const int shy, unsigned* __restrict__ cursor,
+                                                           int2* __restrict__ sorted, int* __restrict__ perm) {
+  __shared__ unsigned cur[kBins];
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) cur[i] = 0;
+  __syncthreads();
+  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cur[bin_of(xy[i], rb, shx, shy)], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    if (cur[i]) cur[i] = atomicAdd(&cursor[i], cur[i]);
+  __syncthreads();
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int2 p = xy[i];
+    const unsigned pos = atomicAdd(&cur[bin_of(p, rb, shx, shy)], 1u);
+    sorted[pos] = p;
+    perm[pos] = (int)i;
+  }
+}
+
+template <int kChunkShift>
+__global__ __launch_bounds__(kBlock) void map_sorted_kernel(const KIndex ix, const int2* __restrict__ xy,
+                                                            const int* __restrict__ perm, const long long n,
+                                                            int* __restrict__ out) {
+  __shared__ WaveLds wl[kWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  WaveLds& S = wl[threadIdx.x / kWave];
+  const long long ntiles = (n + kWave - 1) / kWave;
+  const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
+  for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
+       t += nwaves) {
+    const long long i0 = t * kWave;
+    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kWave, n - i0), out, perm + i0);
+  }
+}
+
 // Quantiser: q = rint(v * 2^22) + 2^30 per axis; invalid input -> (-1, -1).
 // The product by a power of two is exact, so rint is the only rounding.
 __global__ __launch_bounds__(256) void quantize_kernel(const double2* __restrict__ ll,
@@ -427,27 +544,73 @@ __global__ __launch_bounds__(256) void quantize_kernel(const double2* __restrict
 
 }  // namespace
 
-hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
-                      const Tuning& t, int num_cu, hipStream_t stream) {
+static long long grid_blocks(long long n, const Tuning& t, int num_cu) {
   const long long tiles = (n + kWave - 1) / kWave;
   long long blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   const long long cap = (long long)num_cu * t.blocks_per_cu;
   if (blocks > cap) blocks = cap;
-  if (blocks < 1) blocks = 1;
-  const dim3 grid((unsigned)blocks), block(kBlock);
+  return blocks < 1 ? 1 : blocks;
+}
+
+template <int kShift>
+static void launch_plain(const KIndex& ix, const int2* p, long long n, int* out, dim3 grid, hipStream_t stream) {
+  hipLaunchKernelGGL(map_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, p, n, out);
+}
+
+template <int kShift>
+static void launch_sorted(const KIndex& ix, const int2* p, const int* perm, long long n, int* out, dim3 grid,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(map_sorted_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, p, perm, n, out);
+}
+
+hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
+                      const Tuning& t, int num_cu, hipStream_t stream) {
   const int2* p = reinterpret_cast<const int2*>(xy);
-  switch (t.edge_chunk) {
-    case 4:
-      hipLaunchKernelGGL(map_kernel<2>, grid, block, 0, stream, ix, p, (long long)n, out);
-      break;
-    case 16:
-      hipLaunchKernelGGL(map_kernel<4>, grid, block, 0, stream, ix, p, (long long)n, out);
-      break;
-    default:
-      hipLaunchKernelGGL(map_kernel<3>, grid, block, 0, stream, ix, p, (long long)n, out);
-      break;
+  const dim3 grid((unsigned)grid_blocks(n, t, num_cu));
+  const bool presort = t.presort && n >= kPresortMin && ix.root_box.x < ix.root_box.y &&
+                       ix.root_box.z < ix.root_box.w;
+  if (!presort) {
+    switch (t.edge_chunk) {
+      case 8: launch_plain<3>(ix, p, n, out, grid, stream); break;
+      case 16: launch_plain<4>(ix, p, n, out, grid, stream); break;
+      default: launch_plain<2>(ix, p, n, out, grid, stream); break;
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  // spatially sorted, chunk by chunk, through stream-ordered scratch
+  const long long chunk = std::min<long long>(n, kPresortChunk);
+  const int nblk = kBinBlocks;
+  const size_t hist_bytes = sizeof(unsigned) * 2 * (size_t)kBins;
+  const size_t bytes = hist_bytes + (size_t)chunk * (sizeof(int2) + sizeof(int)) + 256;
+  void* scratch = nullptr;
+  hipError_t e = hipMallocAsync(&scratch, bytes, stream);
+  if (e != hipSuccess) return e;
+  unsigned* tot = static_cast<unsigned*>(scratch);
+  unsigned* cursor = tot + kBins;
+  int2* sorted = reinterpret_cast<int2*>(static_cast<char*>(scratch) + hist_bytes);
+  int* perm = reinterpret_cast<int*>(sorted + chunk);
+  const int4 rb = ix.root_box;
+  int shx = 0, shy = 0;
+  while (((1ll << kBinBits) << shx) < (long long)rb.y - rb.x) ++shx;
+  while (((1ll << kBinBits) << shy) < (long long)rb.w - rb.z) ++shy;
+  hipLaunchKernelGGL(bin_zero_kernel, dim3(1), dim3(1024), 0, stream, tot);
+  for (long long c0 = 0; c0 < n && e == hipSuccess; c0 += chunk) {
+    const long long m = std::min(chunk, (long long)n - c0);
+    const long long per = (m + nblk - 1) / nblk;
+    hipLaunchKernelGGL(bin_count_kernel, dim3(nblk), dim3(1024), 0, stream, p + c0, m, per, rb, shx, shy, tot);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, stream, tot, cursor);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk), dim3(1024), 0, stream, p + c0, m, per, rb, shx, shy, cursor,
+                       sorted, perm);
+    const dim3 g2((unsigned)grid_blocks(m, t, num_cu));
+    switch (t.edge_chunk) {
+      case 8: launch_sorted<3>(ix, sorted, perm, m, out + c0, g2, stream); break;
+      case 16: launch_sorted<4>(ix, sorted, perm, m, out + c0, g2, stream); break;
+      default: launch_sorted<2>(ix, sorted, perm, m, out + c0, g2, stream); break;
+    }
+    e = hipGetLastError();
+  }
+  const hipError_t e2 = hipFreeAsync(scratch, stream);
+  return e != hipSuccess ? e : e2;
 }
 
 hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, const BatchEntry* tab,

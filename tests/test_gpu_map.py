@@ -111,6 +111,23 @@ def test_config2_two_million_vs_hierarchy_oracle(torch_cuda, bm, cfg2):
     assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all()
 
 
+def test_spatial_presort_never_changes_results(torch_cuda, bm, cfg2):
+    """Calls above the pre-sort threshold, sorted or not, several chunks with
+    a ragged tail: identical outputs, equal to the oracle on a sample."""
+    torch = torch_cuda
+    g, ix, H = cfg2
+    n = 3 * (1 << 22) + 12345
+    pts = synth.points(2, n, i0=5_000_000)
+    xy = torch.from_numpy(pts).cuda()
+    say("presort on/off", n)
+    a = bm.map_points(ix, xy, tuning=bm.Tuning(4, 5, 2048, 1))
+    b = bm.map_points(ix, xy, tuning=bm.Tuning(8, 3, 2048, 0))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    sub = np.random.default_rng(8).choice(n, 100_000, replace=False)
+    assert (a.cpu().numpy()[sub] == H.map(pts[sub])).all()
+
+
 def test_config2_full_size_sampled_and_partition_property(torch_cuda, bm, cfg2):
     """100M points in the benchmark's launch shape: sampled outputs against the
     oracle, and at every point the partition property (an id exactly when the
@@ -361,6 +378,7 @@ def test_autotune_never_changes_results(torch_cuda, bm, cfg2, tmp_path, monkeypa
     say("autotune")
     t = bm.autotune(ix, xy)
     assert t.edge_chunk in (4, 8) and 3 <= t.blocks_per_cu <= 6 and t.tile_points in (512, 2048, 8192)
+    assert t.presort in (0, 1)
     t2 = bm.autotune(ix, xy)  # from the cache
     assert t2.as_dict() == t.as_dict()
     assert torch.equal(bm.map_points(ix, xy, tuning=t), bm.map_points(ix, xy))
