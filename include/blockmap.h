@@ -302,6 +302,19 @@ int bm_server_run_trace(bm_server* srv, const bm_request* reqs, int64_t nreq, co
  * are dropped. No call on the server may be running. */
 void bm_server_destroy(bm_server* srv);
 
+/* Measurement aid: as map_points_tuned, but with HIP events recorded on
+ * `stream` around each launch of the mapping kernel and each spatial-sort
+ * phase; waits for the stream and returns the summed durations. */
+typedef struct {
+  double map_ms;          /* mapping-kernel launches */
+  double sort_ms;         /* spatial pre-sort phases (0 when not sorted) */
+  int32_t map_launches;
+  int32_t sort_launches;
+} bm_launch_times;
+
+int map_points_timed(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
+                     const bm_tuning* t, hipStream_t stream, bm_launch_times* times);
+
 /* Error text for the last failing call on this thread ("" if none). */
 const char* bm_last_error(void);
 

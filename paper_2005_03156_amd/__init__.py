@@ -53,6 +53,15 @@ class Tuning(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class LaunchTimes(C.Structure):
+    _fields_ = [("map_ms", C.c_double), ("sort_ms", C.c_double), ("map_launches", C.c_int32),
+                ("sort_launches", C.c_int32)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
 class Batch(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("out_ids", C.c_void_p), ("n", C.c_int64)]
 
@@ -92,6 +101,7 @@ _SIGS = {
     "map_points": (C.c_int, [_P, _P, _I64, _P, _P]),
     "map_points_tuned": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P]),
     "bm_quantize_lonlat": (C.c_int, [_P, _I64, _P, _P]),
+    "map_points_timed": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P, C.POINTER(LaunchTimes)]),
     "bm_tuning_default": (C.c_int, [C.POINTER(Tuning)]),
     "bm_autotune": (C.c_int, [_P, _P, _I64, C.POINTER(Tuning), _P]),
     "bm_map_batches": (C.c_int, [_P, _P, _I64, C.POINTER(Tuning), _P]),
@@ -230,6 +240,16 @@ def map_points(index: Index, xy, out=None, stream=None, tuning: Tuning | None = 
     else:
         _check(lib.map_points_tuned(index.handle, pxy, n, pout, C.byref(tuning), s))
     return out
+
+
+def map_points_timed(index: Index, xy, out, stream=None, tuning: Tuning | None = None) -> dict:
+    """map_points with event timing of the mapping-kernel launches and of the
+    spatial-sort phases (waits for the stream)."""
+    t = LaunchTimes()
+    _check(lib.map_points_timed(index.handle, _dev_ptr(xy, "int32", (2,)), xy.shape[0], _dev_ptr(out, "int32"),
+                                C.byref(tuning) if tuning is not None else None, _stream_handle(stream),
+                                C.byref(t)))
+    return t.as_dict()
 
 
 def quantize_lonlat(lonlat, out=None, stream=None):

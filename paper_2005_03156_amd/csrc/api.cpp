@@ -145,6 +145,42 @@ __attribute__((visibility("default"))) int map_points_tuned(const bm_index* inde
   BM_GUARD("map_points")
 }
 
+__attribute__((visibility("default"))) int map_points_timed(const bm_index* index, const int32_t* xy, int64_t n,
+                                                           int32_t* out_ids, const bm_tuning* t, hipStream_t stream,
+                                                           bm_launch_times* times) {
+  try {
+    if (!index || !times) return fail(BM_EINVAL, "map_points_timed: null argument");
+    if (n < 0) return fail(BM_EINVAL, "map_points_timed: n < 0");
+    if (n > 0 && (!xy || !out_ids)) return fail(BM_EINVAL, "map_points_timed: null buffer");
+    int rc = check_device(index, "map_points_timed");
+    if (rc != BM_OK) return rc;
+    LaunchTimer* tm = new (std::nothrow) LaunchTimer();
+    if (!tm) return fail(BM_ENOMEM, "map_points_timed: out of host memory");
+    hipError_t e = hipSuccess;
+    int made = 0;
+    for (; made < LaunchTimer::kMax && e == hipSuccess; ++made) e = hipEventCreate(&tm->ev[made]);
+    if (e == hipSuccess && n > 0) e = launch_map(index->k, xy, n, out_ids, tuning_from(t), index->num_cu, stream, tm);
+    if (e == hipSuccess && tm->n > 0) e = hipEventSynchronize(tm->ev[tm->n - 1]);
+    double map_ms = 0, sort_ms = 0;
+    int maps = 0, sorts = 0;
+    for (int i = 0; e == hipSuccess && i + 1 < tm->n; ++i) {
+      float ms = 0;
+      e = hipEventElapsedTime(&ms, tm->ev[i], tm->ev[i + 1]);
+      if (tm->tag[i] == 0 && tm->tag[i + 1] == 1) { map_ms += ms; ++maps; }
+      if (tm->tag[i] == 2 && tm->tag[i + 1] == 0) { sort_ms += ms; ++sorts; }
+    }
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(tm->ev[i]);
+    delete tm;
+    if (e != hipSuccess) return fail(BM_EHIP, std::string("map_points_timed: ") + hipGetErrorString(e));
+    times->map_ms = map_ms;
+    times->sort_ms = sort_ms;
+    times->map_launches = maps;
+    times->sort_launches = sorts;
+    return BM_OK;
+  }
+  BM_GUARD("map_points_timed")
+}
+
 __attribute__((visibility("default"))) int map_points(const bm_index* index, const int32_t* xy, int64_t n,
                                                      int32_t* out_ids, hipStream_t stream) {
   return map_points_tuned(index, xy, n, out_ids, nullptr, stream);

@@ -72,9 +72,19 @@ struct Tuning {
 
 Tuning tuning_from(const bm_tuning* t);
 
+// Optional event marks around the launches of one mapping call: tag 0 opens
+// and tag 1 closes a mapping-kernel launch; tag 2 opens a sort phase (closed
+// by the next tag 0).
+struct LaunchTimer {
+  static constexpr int kMax = 1024;
+  hipEvent_t ev[kMax];
+  int tag[kMax];
+  int n = 0;
+};
+
 // Launchers (map_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
-                      const Tuning& t, int num_cu, hipStream_t stream);
+                      const Tuning& t, int num_cu, hipStream_t stream, LaunchTimer* timer = nullptr);
 // Batched form: meta must hold nb + 3 int64 (nb, work counter, prefix).
 hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, const BatchEntry* tab,
                           long long* meta, const Tuning& t, int num_cu, hipStream_t stream);

@@ -564,17 +564,25 @@ static void launch_sorted(const KIndex& ix, const int2* p, const int* perm, long
 }
 
 hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
-                      const Tuning& t, int num_cu, hipStream_t stream) {
+                      const Tuning& t, int num_cu, hipStream_t stream, LaunchTimer* timer) {
   const int2* p = reinterpret_cast<const int2*>(xy);
+  auto mark = [&](int slot) {
+    if (timer && timer->n < LaunchTimer::kMax) {
+      (void)hipEventRecord(timer->ev[timer->n], stream);
+      timer->tag[timer->n++] = slot;
+    }
+  };
   const dim3 grid((unsigned)grid_blocks(n, t, num_cu));
   const bool presort = t.presort && n >= kPresortMin && ix.root_box.x < ix.root_box.y &&
                        ix.root_box.z < ix.root_box.w;
   if (!presort) {
+    mark(0);
     switch (t.edge_chunk) {
       case 8: launch_plain<3>(ix, p, n, out, grid, stream); break;
       case 16: launch_plain<4>(ix, p, n, out, grid, stream); break;
       default: launch_plain<2>(ix, p, n, out, grid, stream); break;
     }
+    mark(1);
     return hipGetLastError();
   }
   // spatially sorted, chunk by chunk, through stream-ordered scratch
@@ -597,16 +605,19 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
   for (long long c0 = 0; c0 < n && e == hipSuccess; c0 += chunk) {
     const long long m = std::min(chunk, (long long)n - c0);
     const long long per = (m + nblk - 1) / nblk;
+    mark(2);
     hipLaunchKernelGGL(bin_count_kernel, dim3(nblk), dim3(1024), 0, stream, p + c0, m, per, rb, shx, shy, tot);
     hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, stream, tot, cursor);
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk), dim3(1024), 0, stream, p + c0, m, per, rb, shx, shy, cursor,
                        sorted, perm);
     const dim3 g2((unsigned)grid_blocks(m, t, num_cu));
+    mark(0);
     switch (t.edge_chunk) {
       case 8: launch_sorted<3>(ix, sorted, perm, m, out + c0, g2, stream); break;
       case 16: launch_sorted<4>(ix, sorted, perm, m, out + c0, g2, stream); break;
       default: launch_sorted<2>(ix, sorted, perm, m, out + c0, g2, stream); break;
     }
+    mark(1);
     e = hipGetLastError();
   }
   const hipError_t e2 = hipFreeAsync(scratch, stream);
