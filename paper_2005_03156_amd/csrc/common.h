@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime_api.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <string>
@@ -35,6 +36,16 @@ struct alignas(64) LeafRec {
   unsigned char off[32];  // inline slab offsets (K + 1 <= 32, all <= 255), relative to ent
 };
 constexpr int kLeafExtOff = 1 << 24;  // offsets are K + 1 uint32 stored in the int4s before ent
+static_assert(sizeof(GroupRec) == 32 && sizeof(LeafRec) == 64, "record sizes");
+static_assert(offsetof(LeafRec, ent) == 16 && offsetof(LeafRec, leaf_id) == 24 && offsetof(LeafRec, packed) == 28,
+              "the kernels read ent, leaf_id and packed as one int4");
+
+// Kernel-side limits: a candidate item packs a node id with a 6-bit lane, and
+// edge-list positions are 32-bit. The device copy of `ent` carries kEntPad
+// zero entries at its end, so a crossing-test chunk may load past its list.
+constexpr long long kMaxNodes = 1ll << 26;
+constexpr long long kMaxEnt = (1ll << 31) - 64;
+constexpr int kEntPad = 16;
 
 struct KIndex {
   const GroupRec* grp;        // [leaf_base]

@@ -159,7 +159,8 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   }
   size[L] = B;
   total_nodes += B;
-  if (total_nodes > INT32_MAX) return fail(BM_ERANGE, "bm_index_create: too many nodes");
+  if (total_nodes > kMaxNodes)
+    return fail(BM_ERANGE, "bm_index_create: more than 2^26 nodes (groups of all levels plus blocks)");
 
   // rings
   if (B > 0) {
@@ -277,6 +278,8 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
     h.grp[g].child = make_table(box_of, h.grp[g].child.x, h.grp[g].child.y, h.grp[g].box, h.slot_mask);
   int4 rb = kEmptyBox;
   for (int64_t e = 0; e < size[0]; ++e) grow(rb, box_of(e));
+  if ((int64_t)h.ent.size() > kMaxEnt)
+    return fail(BM_ERANGE, "bm_index_create: the slab edge lists exceed 2^31 entries");
   h.root_box = rb;
   h.root_child = make_table(box_of, 0, (int)size[0], rb, h.slot_mask);
   h.n_levels = L;
@@ -286,10 +289,11 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   return BM_OK;
 }
 
+// Device copy of v followed by `pad` zeroed elements.
 template <class T>
-int upload(bm_index* ix, const std::vector<T>& v, const T** dst) {
+int upload(bm_index* ix, const std::vector<T>& v, const T** dst, size_t pad = 0) {
   void* p = nullptr;
-  const size_t bytes = std::max<size_t>(v.size() * sizeof(T), sizeof(T));
+  const size_t bytes = std::max<size_t>((v.size() + pad) * sizeof(T), sizeof(T));
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     return fail(e == hipErrorOutOfMemory ? BM_ENOMEM : BM_EHIP,
@@ -300,6 +304,10 @@ int upload(bm_index* ix, const std::vector<T>& v, const T** dst) {
   if (!v.empty()) {
     e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(BM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  if (pad) {
+    e = hipMemset(static_cast<T*>(p) + v.size(), 0, pad * sizeof(T));
+    if (e != hipSuccess) return fail(BM_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
   }
   *dst = static_cast<const T*>(p);
   return BM_OK;
@@ -325,7 +333,7 @@ int make_device(HostIndex& h, bm_index** out) {
   int rc = BM_OK;
   if (rc == BM_OK) rc = upload(ix, h.grp, &k.grp);
   if (rc == BM_OK) rc = upload(ix, h.leaf, &k.leaf);
-  if (rc == BM_OK) rc = upload(ix, h.ent, &k.ent);
+  if (rc == BM_OK) rc = upload(ix, h.ent, &k.ent, kEntPad);
   if (rc == BM_OK) rc = upload(ix, h.slot_mask, reinterpret_cast<const uint64_t**>(&k.slot_mask));
   if (rc == BM_OK) rc = upload(ix, h.parent, &k.parent);
   if (rc != BM_OK) {
@@ -393,6 +401,7 @@ bool consistent(const HostIndex& h) {
       (int64_t)h.leaf.size() != B || h.g0 > N || (h.n_levels == 0 ? h.g0 != B : h.g0 > lb))
     return false;
   const int64_t NE = (int64_t)h.ent.size();
+  if (N > kMaxNodes || NE > kMaxEnt) return false;
   auto table_ok = [&](const int4& c) {
     if (c.z < 0) return true;
     const int logS = c.w & 0xff, shx = (c.w >> 8) & 0xff, shy = (c.w >> 16) & 0xff, m = c.y - c.x;

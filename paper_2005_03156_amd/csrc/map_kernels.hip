@@ -30,17 +30,17 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kCap = 256;       // (node, point) items per list per wave
 constexpr int kCapChunk = 256;  // crossing-test chunks per window per wave
+constexpr int kLaneBits = 6;    // an item is node << kLaneBits | point lane
+static_assert((1 << kLaneBits) == kWave, "lane field");
 
 struct WaveLds {
   int2 pts[kWave];
   unsigned best[kWave];
-  unsigned par[kWave];            // crossing parity of the pairs of one round
-  unsigned node[2][kCap];
-  unsigned char lane[2][kCap];
+  unsigned par[kWave];     // crossing parity of the pairs of one round
+  uint4 pair[kWave];       // per pair of a round: first listed edge, edges, first chunk, point lane
+  unsigned item[2][kCap];  // (node, point) lists of the current and the next level
   unsigned char ovf[kWave];
-  unsigned long long ch_j0[kCapChunk];  // first entry of a chunk in `ent`
-  unsigned char ch_q[kCapChunk];        // pair (within the round) of a chunk
-  unsigned char ch_n[kCapChunk];        // edges in the chunk
+  unsigned char ch_q[kCapChunk];  // pair (within the round) of each chunk of a window
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -55,10 +55,10 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
-__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v, int lane) {
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v, int lane) {
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
-    const unsigned long long t = __shfl_up(v, o);
+    const unsigned t = __shfl_up(v, o);
     if (lane >= o) v += t;
   }
   return v;
@@ -94,33 +94,35 @@ __device__ __forceinline__ int4 node_box(const KIndex& ix, int e) {
   return e >= ix.leaf_base ? ix.leaf[e - ix.leaf_base].box : ix.grp[e].box;
 }
 
-// The slab of leaf record r holding height py (which lies in the leaf's
-// y-extent) as a range [first, end) of `ent`.
-__device__ __forceinline__ void slab_range(const KIndex& ix, const LeafRec& r, const int leaf, const int py,
-                                           long long& first, unsigned& len) {
-  const int sh = r.packed & 0xff, logK = (r.packed >> 8) & 0xff;
-  const int b = (int)(((long long)py - r.box.z) >> sh);
+// The slab of leaf `leaf` holding height py (py lies in the leaf's y-extent)
+// as a range [first, first + len) of `ent`; also the leaf's block index.
+__device__ __forceinline__ void slab_range(const KIndex& ix, const int leaf, const int py, unsigned& first,
+                                           unsigned& len, unsigned& bid) {
+  const LeafRec* r = ix.leaf + leaf;
+  const int4 meta = *reinterpret_cast<const int4*>(&r->ent);  // ent (2 words, below 2^31), leaf_id, packed
+  const unsigned ent = (unsigned)meta.x;
+  bid = (unsigned)meta.z;
+  const int packed = meta.w;
+  const int sh = packed & 0xff, logK = (packed >> 8) & 0xff;
+  const unsigned b = ((unsigned)py - (unsigned)r->box.z) >> sh;
   unsigned o0, o1;
-  if (r.packed & kLeafExtOff) {
-    const long long nq = ((1ll << logK) + 1 + 3) >> 2;
-    const unsigned* o = reinterpret_cast<const unsigned*>(ix.ent + r.ent - nq);
+  if (packed & kLeafExtOff) {
+    const unsigned nq = ((1u << logK) + 1u + 3u) >> 2;
+    const unsigned* o = reinterpret_cast<const unsigned*>(ix.ent + (ent - nq));
     o0 = o[b];
     o1 = o[b + 1];
   } else {
-    const unsigned char* o = ix.leaf[leaf].off;
-    o0 = o[b];
-    o1 = o[b + 1];
+    o0 = r->off[b];
+    o1 = r->off[b + 1];
   }
-  first = r.ent + o0;
+  first = ent + o0;
   len = o1 - o0;
 }
 
 // Crossing parity of a point against one leaf (point inside the leaf box).
 __device__ unsigned leaf_parity(const KIndex& ix, int leaf, int2 p) {
-  const LeafRec r = ix.leaf[leaf];
-  long long first;
-  unsigned len;
-  slab_range(ix, r, leaf, p.y, first, len);
+  unsigned first, len, bid;
+  slab_range(ix, leaf, p.y, first, len, bid);
   unsigned acc = 0;
   for (unsigned j = 0; j < len; ++j) {
     const int4 e = ix.ent[first + j];
@@ -161,23 +163,42 @@ __device__ unsigned walk_point(const KIndex& ix, int2 p) {
   return best;
 }
 
-// Append (node, point lane) to list `dst` (wave-uniform count `cnt`) for
+// Append item (node, point lane) to list `dst` (wave-uniform count `cnt`) for
 // every lane where `pred` holds; all 64 lanes must be active. Items that do
 // not fit mark their point for the depth-first fallback.
 __device__ __forceinline__ void emit(WaveLds& S, int dst, bool pred, unsigned node, int plane,
                                      unsigned& cnt) {
   const unsigned long long m = __ballot(pred);
   if (m == 0ull) return;
+  const unsigned k = (unsigned)__popcll(m);
   const unsigned slot = cnt + lanes_below(m);
-  if (pred) {
-    if (slot < (unsigned)kCap) {
-      S.node[dst][slot] = node;
-      S.lane[dst][slot] = (unsigned char)plane;
-    } else {
+  const unsigned it = (node << kLaneBits) | (unsigned)plane;
+  if (cnt + k <= (unsigned)kCap) {  // wave-uniform: every new item fits
+    if (pred) S.item[dst][slot] = it;
+  } else if (pred) {
+    if (slot < (unsigned)kCap)
+      S.item[dst][slot] = it;
+    else
       S.ovf[plane] = 1;
-    }
   }
-  cnt += (unsigned)__popcll(m);
+  cnt += k;
+}
+
+// Where the boxes of one level live: node n's record starts at
+// rec + ((n - sub) << shift), its box first (groups: 32-byte records from
+// node 0, leaves: 64-byte records from leaf_base).
+struct LevelRecs {
+  const char* rec;
+  unsigned sub;
+  int shift;
+};
+
+__device__ __forceinline__ LevelRecs level_recs(const KIndex& ix, const bool leaves) {
+  LevelRecs L;
+  L.rec = leaves ? reinterpret_cast<const char*>(ix.leaf) : reinterpret_cast<const char*>(ix.grp);
+  L.sub = leaves ? (unsigned)ix.leaf_base : 0u;
+  L.shift = leaves ? 6 : 5;
+  return L;
 }
 
 // Children of one group per lane (ci = child record, gb = group box, pp =
@@ -186,8 +207,8 @@ __device__ __forceinline__ void emit(WaveLds& S, int dst, bool pred, unsigned no
 // and the y-slot of pp are tested; otherwise all of them, 64 at a time.
 // Called with all 64 lanes active; `has` masks lanes without an item.
 __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
-                                       const int4 gb, const int2 pp, int pl, int dst,
-                                       unsigned& cnt, const bool leaves) {
+                                       const int4 gb, const int2 pp, int pl, int dst, unsigned& cnt,
+                                       const LevelRecs L) {
   const int m = has ? ci.y - ci.x : 0;
   for (int base = 0; wave_any(base < m); base += 64) {
     unsigned long long cand = 0ull;
@@ -196,43 +217,43 @@ __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, c
       cand = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
       if (ci.z >= 0) {  // slot table (only groups of at most 64 children have one)
         const int logS = ci.w & 0xff, shx = (ci.w >> 8) & 0xff, shy = (ci.w >> 16) & 0xff;
-        const long long dx = (long long)pp.x - gb.x, dy = (long long)pp.y - gb.z;
-        const long long sx = dx >> shx, sy = dy >> shy;
-        const long long S_ = 1ll << logS;
-        if (dx < 0 || dy < 0 || sx >= S_ || sy >= S_)
+        const unsigned S_ = 1u << logS;
+        // exact offsets once pp is known to lie at or above the box's low corner
+        const unsigned sx = ((unsigned)pp.x - (unsigned)gb.x) >> shx;
+        const unsigned sy = ((unsigned)pp.y - (unsigned)gb.z) >> shy;
+        if (pp.x < gb.x || pp.y < gb.z || sx >= S_ || sy >= S_)
           cand = 0ull;
         else
-          cand &= ix.slot_mask[ci.z + sx] & ix.slot_mask[ci.z + S_ + sy];
+          cand &= ix.slot_mask[(unsigned)ci.z + sx] & ix.slot_mask[(unsigned)ci.z + S_ + sy];
       }
     }
-    const int c0 = ci.x + base;
+    const unsigned c0 = (unsigned)(ci.x + base);
     while (wave_any(cand != 0ull)) {
       const bool h1 = cand != 0ull;
-      const int b1 = h1 ? __builtin_ctzll(cand) : 0;
+      const unsigned n1 = h1 ? c0 + (unsigned)__builtin_ctzll(cand) : L.sub;
       cand &= cand - 1ull;
       const bool h2 = cand != 0ull;
-      const int b2 = h2 ? __builtin_ctzll(cand) : 0;
+      const unsigned n2 = h2 ? c0 + (unsigned)__builtin_ctzll(cand) : L.sub;
       cand &= cand - 1ull;
-      int4 bx1 = make_int4(0, 0, 0, 0), bx2 = make_int4(0, 0, 0, 0);
-      if (leaves) {
-        if (h1) bx1 = ix.leaf[c0 + b1 - ix.leaf_base].box;
-        if (h2) bx2 = ix.leaf[c0 + b2 - ix.leaf_base].box;
-      } else {
-        if (h1) bx1 = ix.grp[c0 + b1].box;
-        if (h2) bx2 = ix.grp[c0 + b2].box;
-      }
-      emit(S, dst, h1 && in_box(bx1, pp), (unsigned)(c0 + b1), pl, cnt);
-      emit(S, dst, h2 && in_box(bx2, pp), (unsigned)(c0 + b2), pl, cnt);
+      // both loads are issued before either box is used; a lane without a
+      // candidate reads the level's first record
+      const int4 bx1 = *reinterpret_cast<const int4*>(L.rec + ((size_t)(n1 - L.sub) << L.shift));
+      const int4 bx2 = *reinterpret_cast<const int4*>(L.rec + ((size_t)(n2 - L.sub) << L.shift));
+      emit(S, dst, h1 && in_box(bx1, pp), n1, pl, cnt);
+      emit(S, dst, h2 && in_box(bx2, pp), n2, pl, cnt);
     }
   }
 }
 
 // The whole path for one tile of up to 64 points (one per lane); all 64
-// lanes of the wave take part. Writes out[lane] for lanes below nvalid.
+// lanes of the wave take part. Writes the result of lane i < nvalid to
+// out[i], or to out[perm[i]] when a permutation is given (entries outside
+// [0, nperm) are skipped).
 template <int kChunkShift>
 __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int lane,
                                          const int2* __restrict__ xy, const int nvalid,
-                                         int* __restrict__ out, const int* __restrict__ perm = nullptr) {
+                                         int* __restrict__ out, const int* __restrict__ perm = nullptr,
+                                         const long long nperm = 0) {
   constexpr int kChunk = 1 << kChunkShift;
   const bool valid = lane < nvalid;
   const int2 p = valid ? xy[lane] : make_int2(0, 0);
@@ -244,25 +265,22 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
   // ---- the root's children (level 0), one item per point
   int cur = 0;
   unsigned cnt = 0;
-  expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt, ix.n_levels == 0);
+  expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt, level_recs(ix, ix.n_levels == 0));
   cnt = min(cnt, (unsigned)kCap);
   wave_sync();
 
   // ---- lower levels: children of the surviving groups
   for (int l = 0; l < ix.n_levels; ++l) {
     const int nxt = cur ^ 1;
+    const LevelRecs L = level_recs(ix, l + 1 == ix.n_levels);
     unsigned ncnt = 0;
     for (unsigned r = 0; r < cnt; r += kWave) {
       const unsigned q = r + lane;
       const bool has = q < cnt;
-      const unsigned node = has ? S.node[cur][q] : 0u;
-      const int pl = has ? S.lane[cur][q] : 0;
-      int4 ci = make_int4(0, 0, -1, 0), gb = make_int4(0, 0, 0, 0);
-      if (has) {
-        ci = ix.grp[node].child;
-        gb = ix.grp[node].box;
-      }
-      expand(ix, S, has, ci, gb, S.pts[pl], pl, nxt, ncnt, l + 1 == ix.n_levels);
+      const unsigned it = has ? S.item[cur][q] : 0u;  // lanes without an item read group 0
+      const GroupRec* g = ix.grp + (it >> kLaneBits);
+      const int pl = (int)(it & (kWave - 1));
+      expand(ix, S, has, g->child, g->box, S.pts[pl], pl, nxt, ncnt, L);
     }
     cnt = min(ncnt, (unsigned)kCap);
     cur = nxt;
@@ -273,57 +291,58 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
   // pairs per round. A pair only needs the ring edges listed for the y-slab
   // holding its point (the pair passed the leaf's box test, so the point lies
   // in the ring's y-extent); that list is cut into chunks of kChunk edges and
-  // all chunks of the round are dealt across the lanes.
+  // all chunks of the round are dealt across the lanes. The edge list is
+  // padded at its end, so a chunk's loads never leave it.
   for (unsigned r = 0; r < cnt; r += kWave) {
     const unsigned q = r + lane;
     const bool has = q < cnt;
-    long long l0 = 0;
-    unsigned len = 0, bid = 0;
+    unsigned first = 0, len = 0, bid = 0;
+    const unsigned it = has ? S.item[cur][q] : 0u;
+    const int pl = (int)(it & (kWave - 1));
     if (has) {
-      const int leaf = (int)S.node[cur][q] - ix.leaf_base;
-      const int2 pp = S.pts[S.lane[cur][q]];
-      const LeafRec rec = ix.leaf[leaf];
-      bid = (unsigned)rec.leaf_id;
-      slab_range(ix, rec, leaf, pp.y, l0, len);
+      slab_range(ix, (int)(it >> kLaneBits) - ix.leaf_base, S.pts[pl].y, first, len, bid);
     }
-    const unsigned long long nch = (len + kChunk - 1) >> kChunkShift;
-    const unsigned long long incl = wave_incl_scan(nch, lane);
-    const unsigned long long start = incl - nch;
-    const unsigned long long total = __shfl(incl, kWave - 1);
+    const unsigned nch = (len + kChunk - 1) >> kChunkShift;
+    const unsigned incl = wave_incl_scan(nch, lane);
+    const unsigned start = incl - nch;
+    const unsigned total = __shfl(incl, kWave - 1);
+    S.pair[lane] = make_uint4(first, len, start, (unsigned)pl);
     S.par[lane] = 0;
-    for (unsigned long long w = 0; w < total; w += kCapChunk) {
-      const unsigned long long a = max(start, w), b = min(start + nch, w + (unsigned long long)kCapChunk);
-      for (unsigned long long c = a; c < b; ++c) {
-        const unsigned k0 = (unsigned)((c - start) << kChunkShift);
-        S.ch_j0[c - w] = (unsigned long long)(l0 + k0);
-        S.ch_q[c - w] = (unsigned char)lane;
-        S.ch_n[c - w] = (unsigned char)min((unsigned)kChunk, len - k0);
-      }
+    for (unsigned w = 0; w < total; w += kCapChunk) {
+      const unsigned a = max(start, w), b = min(start + nch, w + (unsigned)kCapChunk);
+      for (unsigned c = a; c < b; ++c) S.ch_q[c - w] = (unsigned char)lane;
       wave_sync();
-      const unsigned nw = (unsigned)min((unsigned long long)kCapChunk, total - w);
+      const unsigned nw = min((unsigned)kCapChunk, total - w);
       for (unsigned c = lane; c < nw; c += kWave) {
-        const long long j0 = (long long)S.ch_j0[c];
-        const int ne = S.ch_n[c];
         const unsigned pq = S.ch_q[c];
+        const uint4 pr = S.pair[pq];
+        const unsigned k0 = (w + c - pr.z) << kChunkShift;
+        const unsigned ne = min((unsigned)kChunk, pr.y - k0);
+        const int4* e = ix.ent + (pr.x + k0);
         int4 ev[kChunk];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) ev[u] = (u < ne) ? ix.ent[j0 + u] : make_int4(0, 0, 0, 0);
-        const int2 pp = S.pts[S.lane[cur][r + pq]];
+        for (int u = 0; u < kChunk; ++u) ev[u] = e[u];
+        const int2 pp = S.pts[pr.w];
         unsigned acc = 0;
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
-          acc ^= (u < ne) ? crosses(make_int2(ev[u].x, ev[u].y), make_int2(ev[u].z, ev[u].w), pp) : 0u;
+          acc ^= ((unsigned)u < ne) ? crosses(make_int2(ev[u].x, ev[u].y), make_int2(ev[u].z, ev[u].w), pp) : 0u;
         if (acc) atomicXor(&S.par[pq], 1u);
       }
       wave_sync();
     }
-    if (has && (S.par[lane] & 1u)) atomicMin(&S.best[S.lane[cur][q]], bid);
+    if (has && (S.par[lane] & 1u)) atomicMin(&S.best[pl], bid);
     wave_sync();
   }
 
   unsigned best = S.best[lane];
   if (valid && S.ovf[lane]) best = min(best, walk_point(ix, p));
-  if (valid) out[perm ? perm[lane] : lane] = (int)best;
+  if (valid) {
+    if (!perm)
+      out[lane] = (int)best;
+    else if ((unsigned long long)(long long)perm[lane] < (unsigned long long)nperm)
+      out[perm[lane]] = (int)best;
+  }
   wave_sync();
 }
 
@@ -524,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void map_sorted_kernel(const KIndex ix, con
   for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
        t += nwaves) {
     const long long i0 = t * kWave;
-    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kWave, n - i0), out, perm + i0);
+    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kWave, n - i0), out, perm + i0, n);
   }
 }
 
