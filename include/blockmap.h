@@ -158,7 +158,7 @@ int bm_quantize_lonlat(const double* lonlat, int64_t n, int32_t* xy, hipStream_t
 
 typedef struct {
   int32_t edge_chunk;       /* ring edges per crossing-test work item: 4, 8 or 16 */
-  int32_t blocks_per_cu;    /* resident workgroups per compute unit (1..8) */
+  int32_t blocks_per_cu;    /* workgroups per compute unit (1..8), capped at what fits */
   int32_t tile_points;      /* batched form: points per unit of work (multiple of 64, <= 2^20) */
   int32_t presort;          /* 1: a call of at least 2^20 points is first counting-sorted by a
                                spatial key (a 64 x 64 Morton grid over the index), 2^22 points

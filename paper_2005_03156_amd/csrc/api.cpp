@@ -29,7 +29,7 @@ void clear_error() { g_err.clear(); }
 const char* error_text() { return g_err.c_str(); }
 
 Tuning tuning_from(const bm_tuning* t) {
-  Tuning r{4, 5, 2048, 1};
+  Tuning r{4, 8, 2048, 1};
   if (t) {
     if (t->presort == 0 || t->presort == 1) r.presort = t->presort;
     if (t->edge_chunk == 4 || t->edge_chunk == 8 || t->edge_chunk == 16) r.edge_chunk = t->edge_chunk;

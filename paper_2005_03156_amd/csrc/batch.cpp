@@ -268,7 +268,7 @@ __attribute__((visibility("default"))) int bm_autotune(const bm_index* index, co
     Tuning best = tuning_from(nullptr);
     float best_ms = 1e30f;
     const int chunks[2] = {4, 8};
-    const int bpcs[4] = {3, 4, 5, 6};
+    const int bpcs[3] = {4, 6, 8};
     for (int c : chunks)
       for (int b : bpcs) {
         Tuning t{c, b, best.tile_points, 1};

@@ -40,10 +40,18 @@ static_assert(sizeof(GroupRec) == 32 && sizeof(LeafRec) == 64, "record sizes");
 static_assert(offsetof(LeafRec, ent) == 16 && offsetof(LeafRec, leaf_id) == 24 && offsetof(LeafRec, packed) == 28,
               "the kernels read ent, leaf_id and packed as one int4");
 
-// Kernel-side limits: a candidate item packs a node id with a 6-bit lane, and
-// edge-list positions are 32-bit. The device copy of `ent` carries kEntPad
-// zero entries at its end, so a crossing-test chunk may load past its list.
-constexpr long long kMaxNodes = 1ll << 26;
+// A wavefront maps a tile of 64 * kTilePts points (kTilePts per lane).
+// Kernel-side limits: a candidate item packs a node id with the point's slot
+// in the tile (kSlotBits), and edge-list positions are 32-bit. The device copy
+// of `ent` carries kEntPad zero entries at its end, so a crossing-test chunk
+// may load past its list.
+#ifndef BM_TILE_PTS
+#define BM_TILE_PTS 2
+#endif
+constexpr int kTilePts = BM_TILE_PTS;
+static_assert(kTilePts == 1 || kTilePts == 2 || kTilePts == 4, "1, 2 or 4 points per lane");
+constexpr int kSlotBits = kTilePts == 4 ? 8 : kTilePts == 2 ? 7 : 6;
+constexpr long long kMaxNodes = 1ll << (32 - kSlotBits);
 constexpr long long kMaxEnt = (1ll << 31) - 64;
 constexpr int kEntPad = 16;
 

@@ -28,18 +28,25 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
-constexpr int kCap = 256;       // (node, point) items per list per wave
-constexpr int kCapChunk = 256;  // crossing-test chunks per window per wave
-constexpr int kLaneBits = 6;    // an item is node << kLaneBits | point lane
-static_assert((1 << kLaneBits) == kWave, "lane field");
+constexpr int kTile = kWave * kTilePts;  // points per wave tile
+static_assert((1 << kSlotBits) == kTile, "slot field");
+constexpr int kCap = kTile < 128 ? 256 : 2 * kTile;  // (node, point) items per list per wave
+constexpr int kCapChunk = 256;                       // crossing-test chunks per window per wave
+
+// Workgroups per CU the mapping kernels are compiled for (register budget):
+// the 4-edge chunk form fits 7 (7 waves per SIMD); wider chunks hold more
+// edges in registers.
+__host__ __device__ constexpr int map_min_blocks(int chunk_shift) {
+  return chunk_shift == 2 ? 7 : chunk_shift == 3 ? 5 : 4;
+}
 
 struct WaveLds {
-  int2 pts[kWave];
-  unsigned best[kWave];
+  int2 pts[kTile];
+  unsigned best[kTile];
   unsigned par[kWave];     // crossing parity of the pairs of one round
-  uint4 pair[kWave];       // per pair of a round: first listed edge, edges, first chunk, point lane
-  unsigned item[2][kCap];  // (node, point) lists of the current and the next level
-  unsigned char ovf[kWave];
+  uint4 pair[kWave];       // per pair of a round: first listed edge, edges, first chunk, point slot
+  unsigned item[2][kCap];  // (node << kSlotBits | point slot) lists of the current and the next level
+  unsigned char ovf[kTile];
   unsigned char ch_q[kCapChunk];  // pair (within the round) of each chunk of a window
 };
 
@@ -163,7 +170,7 @@ __device__ unsigned walk_point(const KIndex& ix, int2 p) {
   return best;
 }
 
-// Append item (node, point lane) to list `dst` (wave-uniform count `cnt`) for
+// Append item (node, point slot) to list `dst` (wave-uniform count `cnt`) for
 // every lane where `pred` holds; all 64 lanes must be active. Items that do
 // not fit mark their point for the depth-first fallback.
 __device__ __forceinline__ void emit(WaveLds& S, int dst, bool pred, unsigned node, int plane,
@@ -172,7 +179,7 @@ __device__ __forceinline__ void emit(WaveLds& S, int dst, bool pred, unsigned no
   if (m == 0ull) return;
   const unsigned k = (unsigned)__popcll(m);
   const unsigned slot = cnt + lanes_below(m);
-  const unsigned it = (node << kLaneBits) | (unsigned)plane;
+  const unsigned it = (node << kSlotBits) | (unsigned)plane;
   if (cnt + k <= (unsigned)kCap) {  // wave-uniform: every new item fits
     if (pred) S.item[dst][slot] = it;
   } else if (pred) {
@@ -245,27 +252,38 @@ __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, c
   }
 }
 
-// The whole path for one tile of up to 64 points (one per lane); all 64
-// lanes of the wave take part. Writes the result of lane i < nvalid to
-// out[i], or to out[perm[i]] when a permutation is given (entries outside
-// [0, nperm) are skipped).
+// The whole path for one tile of up to kTile points (point j * 64 + lane on
+// lane `lane`); all 64 lanes of the wave take part. Writes the result of
+// point i < nvalid to out[i], or to out[perm[i]] when a permutation is given
+// (entries outside [0, nperm) are skipped). With several points per lane the
+// candidate lists of a level hold the items of all of them, so its rounds of
+// 64 items run nearly full.
 template <int kChunkShift>
 __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int lane,
                                          const int2* __restrict__ xy, const int nvalid,
                                          int* __restrict__ out, const int* __restrict__ perm = nullptr,
                                          const long long nperm = 0) {
   constexpr int kChunk = 1 << kChunkShift;
-  const bool valid = lane < nvalid;
-  const int2 p = valid ? xy[lane] : make_int2(0, 0);
-  S.pts[lane] = p;
-  S.best[lane] = 0xFFFFFFFFu;
-  S.ovf[lane] = 0;
+#pragma unroll
+  for (int j = 0; j < kTilePts; ++j) {
+    const int i = j * kWave + lane;
+    S.pts[i] = i < nvalid ? xy[i] : make_int2(0, 0);
+    S.best[i] = 0xFFFFFFFFu;
+    S.ovf[i] = 0;
+  }
   wave_sync();
 
   // ---- the root's children (level 0), one item per point
   int cur = 0;
   unsigned cnt = 0;
-  expand(ix, S, valid, ix.root_child, ix.root_box, p, lane, cur, cnt, level_recs(ix, ix.n_levels == 0));
+  {
+    const LevelRecs L0 = level_recs(ix, ix.n_levels == 0);
+#pragma unroll
+    for (int j = 0; j < kTilePts; ++j) {
+      const int i = j * kWave + lane;
+      expand(ix, S, i < nvalid, ix.root_child, ix.root_box, S.pts[i], i, cur, cnt, L0);
+    }
+  }
   cnt = min(cnt, (unsigned)kCap);
   wave_sync();
 
@@ -278,8 +296,8 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
       const unsigned q = r + lane;
       const bool has = q < cnt;
       const unsigned it = has ? S.item[cur][q] : 0u;  // lanes without an item read group 0
-      const GroupRec* g = ix.grp + (it >> kLaneBits);
-      const int pl = (int)(it & (kWave - 1));
+      const GroupRec* g = ix.grp + (it >> kSlotBits);
+      const int pl = (int)(it & (kTile - 1));
       expand(ix, S, has, g->child, g->box, S.pts[pl], pl, nxt, ncnt, L);
     }
     cnt = min(ncnt, (unsigned)kCap);
@@ -298,10 +316,8 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
     const bool has = q < cnt;
     unsigned first = 0, len = 0, bid = 0;
     const unsigned it = has ? S.item[cur][q] : 0u;
-    const int pl = (int)(it & (kWave - 1));
-    if (has) {
-      slab_range(ix, (int)(it >> kLaneBits) - ix.leaf_base, S.pts[pl].y, first, len, bid);
-    }
+    const int pl = (int)(it & (kTile - 1));
+    if (has) slab_range(ix, (int)(it >> kSlotBits) - ix.leaf_base, S.pts[pl].y, first, len, bid);
     const unsigned nch = (len + kChunk - 1) >> kChunkShift;
     const unsigned incl = wave_incl_scan(nch, lane);
     const unsigned start = incl - nch;
@@ -335,30 +351,34 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
     wave_sync();
   }
 
-  unsigned best = S.best[lane];
-  if (valid && S.ovf[lane]) best = min(best, walk_point(ix, p));
-  if (valid) {
-    if (!perm)
-      out[lane] = (int)best;
-    else if ((unsigned long long)(long long)perm[lane] < (unsigned long long)nperm)
-      out[perm[lane]] = (int)best;
+#pragma unroll
+  for (int j = 0; j < kTilePts; ++j) {
+    const int i = j * kWave + lane;
+    if (i < nvalid) {
+      unsigned best = S.best[i];
+      if (S.ovf[i]) best = min(best, walk_point(ix, S.pts[i]));
+      if (!perm)
+        out[i] = (int)best;
+      else if ((unsigned long long)(long long)perm[i] < (unsigned long long)nperm)
+        out[perm[i]] = (int)best;
+    }
   }
   wave_sync();
 }
 
-// Plain form: the waves of the grid stride over the 64-point tiles.
+// Plain form: the waves of the grid stride over the tiles.
 template <int kChunkShift>
-__global__ __launch_bounds__(kBlock) void map_kernel(const KIndex ix, const int2* __restrict__ xy,
+__global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void map_kernel(const KIndex ix, const int2* __restrict__ xy,
                                                      const long long n, int* __restrict__ out) {
   __shared__ WaveLds wl[kWavesPerBlock];
   const int lane = threadIdx.x & (kWave - 1);
   WaveLds& S = wl[threadIdx.x / kWave];
-  const long long ntiles = (n + kWave - 1) / kWave;
+  const long long ntiles = (n + kTile - 1) / kTile;
   const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
   for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
        t += nwaves) {
-    const long long i0 = t * kWave;
-    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kWave, n - i0), out + i0);
+    const long long i0 = t * kTile;
+    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kTile, n - i0), out + i0);
   }
 }
 
@@ -401,7 +421,7 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(const long long* __r
 }
 
 template <int kChunkShift>
-__global__ __launch_bounds__(kBlock) void batch_map_kernel(const KIndex ix, const BatchEntry* __restrict__ tab,
+__global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map_kernel(const KIndex ix, const BatchEntry* __restrict__ tab,
                                                            long long* __restrict__ meta, const int unit) {
   __shared__ WaveLds wl[kWavesPerBlock];
   const int lane = threadIdx.x & (kWave - 1);
@@ -425,8 +445,8 @@ __global__ __launch_bounds__(kBlock) void batch_map_kernel(const KIndex ix, cons
     const int2* bxy = reinterpret_cast<const int2*>(d.xy);
     const long long p0 = ((long long)u - prefix[lo]) * unit;
     const long long p1 = min(p0 + unit, (long long)d.n);
-    for (long long i0 = p0; i0 < p1; i0 += kWave)
-      map_tile<kChunkShift>(ix, S, lane, bxy + i0, (int)min((long long)kWave, p1 - i0), d.out + i0);
+    for (long long i0 = p0; i0 < p1; i0 += kTile)
+      map_tile<kChunkShift>(ix, S, lane, bxy + i0, (int)min((long long)kTile, p1 - i0), d.out + i0);
   }
 }
 
@@ -531,19 +551,21 @@ __global__ __launch_bounds__(1024) void bin_scatter_kernel(const int2* __restric
   }
 }
 
+// Sorted form: as the plain form, over the sorted copy, each result going to
+// the point's original position.
 template <int kChunkShift>
-__global__ __launch_bounds__(kBlock) void map_sorted_kernel(const KIndex ix, const int2* __restrict__ xy,
-                                                            const int* __restrict__ perm, const long long n,
-                                                            int* __restrict__ out) {
+__global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void map_sorted_kernel(
+    const KIndex ix, const int2* __restrict__ xy, const int* __restrict__ perm, const long long n,
+    int* __restrict__ out) {
   __shared__ WaveLds wl[kWavesPerBlock];
   const int lane = threadIdx.x & (kWave - 1);
   WaveLds& S = wl[threadIdx.x / kWave];
-  const long long ntiles = (n + kWave - 1) / kWave;
+  const long long ntiles = (n + kTile - 1) / kTile;
   const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
   for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
        t += nwaves) {
-    const long long i0 = t * kWave;
-    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kWave, n - i0), out, perm + i0, n);
+    const long long i0 = t * kTile;
+    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kTile, n - i0), out, perm + i0, n);
   }
 }
 
@@ -563,22 +585,45 @@ __global__ __launch_bounds__(256) void quantize_kernel(const double2* __restrict
 
 }  // namespace
 
+// Workgroups of kKernel that fit on one CU at once (registers and LDS),
+// asked once per kernel.
+template <auto kKernel>
+static int resident_blocks() {
+  static const int r = [] {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kKernel, kBlock, 0) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    return nb;
+  }();
+  return r;
+}
+
+// Grid of a mapping launch: enough workgroups for every wave to have a tile,
+// at most blocks_per_cu per CU, and never more per CU than can be resident
+// (with a static tile split a workgroup that waits for a free CU finishes
+// last and stretches the launch).
+template <auto kKernel>
 static long long grid_blocks(long long n, const Tuning& t, int num_cu) {
-  const long long tiles = (n + kWave - 1) / kWave;
+  const long long tiles = (n + kTile - 1) / kTile;
   long long blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  const long long cap = (long long)num_cu * t.blocks_per_cu;
+  const long long cap = (long long)num_cu * std::min(t.blocks_per_cu, resident_blocks<kKernel>());
   if (blocks > cap) blocks = cap;
   return blocks < 1 ? 1 : blocks;
 }
 
 template <int kShift>
-static void launch_plain(const KIndex& ix, const int2* p, long long n, int* out, dim3 grid, hipStream_t stream) {
+static void launch_plain(const KIndex& ix, const int2* p, long long n, int* out, const Tuning& t, int num_cu,
+                         hipStream_t stream) {
+  const dim3 grid((unsigned)grid_blocks<map_kernel<kShift>>(n, t, num_cu));
   hipLaunchKernelGGL(map_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, p, n, out);
 }
 
 template <int kShift>
-static void launch_sorted(const KIndex& ix, const int2* p, const int* perm, long long n, int* out, dim3 grid,
-                          hipStream_t stream) {
+static void launch_sorted(const KIndex& ix, const int2* p, const int* perm, long long n, int* out, const Tuning& t,
+                          int num_cu, hipStream_t stream) {
+  const dim3 grid((unsigned)grid_blocks<map_sorted_kernel<kShift>>(n, t, num_cu));
   hipLaunchKernelGGL(map_sorted_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, p, perm, n, out);
 }
 
@@ -591,15 +636,14 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
       timer->tag[timer->n++] = slot;
     }
   };
-  const dim3 grid((unsigned)grid_blocks(n, t, num_cu));
   const bool presort = t.presort && n >= kPresortMin && ix.root_box.x < ix.root_box.y &&
                        ix.root_box.z < ix.root_box.w;
   if (!presort) {
     mark(0);
     switch (t.edge_chunk) {
-      case 8: launch_plain<3>(ix, p, n, out, grid, stream); break;
-      case 16: launch_plain<4>(ix, p, n, out, grid, stream); break;
-      default: launch_plain<2>(ix, p, n, out, grid, stream); break;
+      case 8: launch_plain<3>(ix, p, n, out, t, num_cu, stream); break;
+      case 16: launch_plain<4>(ix, p, n, out, t, num_cu, stream); break;
+      default: launch_plain<2>(ix, p, n, out, t, num_cu, stream); break;
     }
     mark(1);
     return hipGetLastError();
@@ -629,12 +673,11 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
     hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, stream, tot, cursor);
     hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk), dim3(1024), 0, stream, p + c0, m, per, rb, shx, shy, cursor,
                        sorted, perm);
-    const dim3 g2((unsigned)grid_blocks(m, t, num_cu));
     mark(0);
     switch (t.edge_chunk) {
-      case 8: launch_sorted<3>(ix, sorted, perm, m, out + c0, g2, stream); break;
-      case 16: launch_sorted<4>(ix, sorted, perm, m, out + c0, g2, stream); break;
-      default: launch_sorted<2>(ix, sorted, perm, m, out + c0, g2, stream); break;
+      case 8: launch_sorted<3>(ix, sorted, perm, m, out + c0, t, num_cu, stream); break;
+      case 16: launch_sorted<4>(ix, sorted, perm, m, out + c0, t, num_cu, stream); break;
+      default: launch_sorted<2>(ix, sorted, perm, m, out + c0, t, num_cu, stream); break;
     }
     mark(1);
     e = hipGetLastError();
@@ -643,22 +686,23 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
   return e != hipSuccess ? e : e2;
 }
 
+template <int kShift>
+static void launch_batch_map(const KIndex& ix, const BatchEntry* tab, long long* meta, const Tuning& t, int num_cu,
+                             hipStream_t stream) {
+  const int per_cu = std::max(1, std::min(t.blocks_per_cu, resident_blocks<batch_map_kernel<kShift>>()));
+  hipLaunchKernelGGL(batch_map_kernel<kShift>, dim3((unsigned)(num_cu * per_cu)), dim3(kBlock), 0, stream, ix, tab,
+                     meta, t.tile_points);
+}
+
 hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, const BatchEntry* tab,
                           long long* meta, const Tuning& t, int num_cu, hipStream_t stream) {
   hipLaunchKernelGGL(batch_prefix_kernel, dim3(1), dim3(1024), 0, stream, hdr, nb, tab, meta, t.tile_points);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)std::max(1, num_cu * t.blocks_per_cu)), block(kBlock);
   switch (t.edge_chunk) {
-    case 4:
-      hipLaunchKernelGGL(batch_map_kernel<2>, grid, block, 0, stream, ix, tab, meta, t.tile_points);
-      break;
-    case 16:
-      hipLaunchKernelGGL(batch_map_kernel<4>, grid, block, 0, stream, ix, tab, meta, t.tile_points);
-      break;
-    default:
-      hipLaunchKernelGGL(batch_map_kernel<3>, grid, block, 0, stream, ix, tab, meta, t.tile_points);
-      break;
+    case 4: launch_batch_map<2>(ix, tab, meta, t, num_cu, stream); break;
+    case 16: launch_batch_map<4>(ix, tab, meta, t, num_cu, stream); break;
+    default: launch_batch_map<3>(ix, tab, meta, t, num_cu, stream); break;
   }
   return hipGetLastError();
 }

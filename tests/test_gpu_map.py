@@ -377,7 +377,7 @@ def test_autotune_never_changes_results(torch_cuda, bm, cfg2, tmp_path, monkeypa
     xy = torch.from_numpy(pts).cuda()
     say("autotune")
     t = bm.autotune(ix, xy)
-    assert t.edge_chunk in (4, 8) and 3 <= t.blocks_per_cu <= 6 and t.tile_points in (512, 2048, 8192)
+    assert t.edge_chunk in (4, 8) and t.blocks_per_cu in (4, 6, 8) and t.tile_points in (512, 2048, 8192)
     assert t.presort in (0, 1)
     t2 = bm.autotune(ix, xy)  # from the cache
     assert t2.as_dict() == t.as_dict()
