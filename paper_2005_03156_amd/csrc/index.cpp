@@ -160,7 +160,8 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   size[L] = B;
   total_nodes += B;
   if (total_nodes > kMaxNodes)
-    return fail(BM_ERANGE, "bm_index_create: more than 2^26 nodes (groups of all levels plus blocks)");
+    return fail(BM_ERANGE, "bm_index_create: more than 2^" + std::to_string(32 - kSlotBits) +
+                               " nodes (groups of all levels plus blocks)");
 
   // rings
   if (B > 0) {
