@@ -42,7 +42,7 @@ def read_traffic(kernel, pts_per_launch):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_%s_config2.json" % kernel)
+    path = os.path.join(ROOT, "profiles", "traffic_%s_grid221k_100m.json" % kernel)
     src = os.path.join(ROOT, "paper_2005_03156_amd", "csrc", "map_kernels.hip")
     try:
         d = json.load(open(path))
@@ -144,7 +144,7 @@ def main():
     achieved = OPS_PER_POINT * pts_per_launch / (kernel_ms * 1e-3) / 1e12
     step_ms = wall * 1e3 / args.steps
     hbm_gbs = BYTES_PER_POINT * n / (step_ms * 1e-3) / 1e9
-    traffic = read_traffic("map_kernel", pts_per_launch)
+    traffic = read_traffic("map_sorted_kernel", pts_per_launch)
     log("dominant kernel: %d launches/step, %.3f ms each (%.0f points), sort phases %.3f ms/step; "
         "%.2f T algorithmic ops/s" % (launches, kernel_ms, pts_per_launch, tm["sort_ms"] / reps, achieved))
     res = {
