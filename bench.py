@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a known-size kernel for counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-cover", action="store_true", help="skip the cell-cover (fast approach) leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--served-requests", type=int, default=20_000)
     ap.add_argument("--config3", action="store_true",
@@ -174,6 +175,8 @@ def main():
         "hbm": {"achieved_GBs": hbm_gbs, "peak_GBs": PEAK_HBM_GBS, "frac": hbm_gbs / PEAK_HBM_GBS,
                 "bytes_per_point": BYTES_PER_POINT},
     }
+    if not args.no_cover:
+        res["cover"] = bench_cover(bm, torch, g, ix, xy, out, args.steps)
     del xy, out
     torch.cuda.empty_cache()
     if not args.no_batched:
@@ -190,6 +193,41 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(g, pts)
     print(json.dumps(res), flush=True)
+
+
+def bench_cover(bm, torch, g, ix, xy, ref, steps):
+    """The cell cover (the paper's fast approach) over the same 100M resident
+    points: build time and size, exact and approximate throughput. `ref` holds
+    the plain path's output for the same points."""
+    t0 = time.time()
+    cv = bm.Cover.from_geometry(ix, g)
+    info = cv.info()
+    log("cover: built in %.1fs (wall %.1fs): %s" % (info["build_seconds"], time.time() - t0, info))
+    n = xy.shape[0]
+    out = torch.empty_like(ref)
+    s = torch.cuda.current_stream()
+    r = {"build_seconds": info["build_seconds"], "device_bytes": info["device_bytes"],
+         "cell_log2": info["cell_log2"], "trie_levels": info["trie_levels"],
+         "boundary_cells": info["boundary_cells"], "trie_entries": info["trie_entries"]}
+    for mode in ("exact", "approx"):
+        approx = mode == "approx"
+        bm.map_points_cover(cv, xy, out, approx=approx, stream=s)
+        torch.cuda.synchronize()
+        same = float((out == ref).float().mean().item())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t = time.perf_counter()
+        e0.record(s)
+        for _ in range(steps):
+            bm.map_points_cover(cv, xy, out, approx=approx, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps
+        r[mode] = {"points_per_s": n / wall, "ms_per_step": wall * 1e3,
+                   "kernel_ms": e0.elapsed_time(e1) / steps, "agree_with_plain": same}
+        log("cover %s: %.3f ms/step, %.3g points/s, agrees with the plain path on %.6f of the points" %
+            (mode, wall * 1e3, n / wall, same))
+    cv.close()
+    return r
 
 
 def bench_batched(bm, torch, g, ix, nb=10_000):

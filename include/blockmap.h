@@ -317,6 +317,80 @@ typedef struct {
 int map_points_timed(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
                      const bm_tuning* t, hipStream_t stream, bm_launch_times* times);
 
+/* ---- Cell cover: the fast approach (paper Sec. IV, true-hit filtering) ----
+ *
+ * A cover cuts the plane into non-overlapping square cells of a quadtree over
+ * the index's root box and indexes them with a radix trie that consumes four
+ * quadtree levels (4 bits of each coordinate, a 256-way node) per trie level,
+ * as the paper's F4 trie does; the last trie level takes the remaining 1-4
+ * quadtree levels. A cell that no block edge enters lies wholly inside one
+ * block (an interior cell, which stores that block) or outside every block
+ * (empty); a point there gets its answer from the trie alone. Cells an edge
+ * enters are split down to side 2^cell_log2 and become boundary cells, which
+ * list every block that can hold one of their points and store the answer at
+ * their centre.
+ *
+ * Exact mode returns exactly what map_points returns. Approximate mode skips
+ * the crossing test: a point in a boundary cell gets the exact answer at the
+ * centre of that cell, so every answer is exact at the point itself or at a
+ * point no farther than 2^(cell_log2 - 1) * sqrt(2) from it (the paper's
+ * user-defined precision); points in interior and empty cells are exact. */
+typedef struct bm_cover bm_cover;
+
+typedef struct {
+  int32_t cell_log2; /* side of the finest (boundary) cells = 2^cell_log2 coordinate units, 1..30;
+                        0 = automatic: about 1/32 of the median block's box side, but no finer
+                        than the total ring length / 2^25 (bounds the number of boundary cells) */
+  int32_t threads;   /* host threads for the build; 0 = all */
+} bm_cover_cfg;
+
+typedef struct {
+  int32_t origin_x, origin_y; /* low corner of the covered square */
+  int32_t log2_side;          /* the square's side is 2^log2_side */
+  int32_t trie_levels;
+  int32_t last_level_bits;    /* quadtree levels in the last trie level (the others: 4) */
+  int32_t cell_log2;          /* finest cell side 2^cell_log2 */
+  int64_t trie_entries;       /* 4-byte entries over all trie nodes */
+  int64_t interior_entries, node_entries, boundary_cells, empty_entries;
+  int64_t cell_leaves;        /* listed blocks over all boundary cells */
+  int64_t device_bytes;       /* device memory held by the cover (the index not counted) */
+  double build_seconds;       /* host build time, including the copy of the index to the host */
+} bm_cover_info;
+
+/* Build the cover of `index` on the host (threads as configured; cfg may be
+ * null) and copy it to the index's device. Synchronous. `desc` must be the
+ * descriptor the index was built from (only its rings are read, during the
+ * call): the index keeps just the edges that can cross a ray, and a cell's
+ * uniformity depends on every edge, horizontal ones too. The cover refers to
+ * the index for the crossing tests: the index must outlive it.
+ * Errors: BM_EINVAL (null pointer, cell_log2 out of range, a descriptor whose
+ * rings do not match the index), BM_ERANGE (more than 2^30 trie entries or
+ * cells: raise cell_log2), BM_ENOMEM, BM_EHIP. */
+int bm_cover_create(const bm_index* index, const bm_index_desc* desc, const bm_cover_cfg* cfg, bm_cover** out);
+
+/* Free the cover's device memory (null accepted); no queued work may use it. */
+void bm_cover_destroy(bm_cover* cover);
+
+int bm_cover_get_info(const bm_cover* cover, bm_cover_info* info);
+
+/* Host-only: build the index and its cover from a descriptor and write the
+ * cover to `path` ("BMCOV001", then the shape as 6 int32 (origin x, y, log2
+ * side, trie levels, last-level bits, cell_log2), 4 int64 entry counts
+ * (interior, node, boundary, empty), and the arrays trie entries (uint32),
+ * cell offsets (uint32), cell blocks (uint32 leaf positions in the index
+ * file's leaf order) and cell centre answers (int32), each as an int64
+ * length followed by the data). No GPU is needed. */
+int bm_cover_build_file(const bm_index_desc* desc, const bm_cover_cfg* cfg, const char* path);
+
+/* Map n points (device xy, as map_points) through the cover into out_ids
+ * (device, n int32). approx = 0: exact, identical to map_points; approx = 1:
+ * boundary cells answer with their centre's block (see above). Asynchronous
+ * on `stream`; `stream` must belong to the cover's device.
+ * Errors: BM_EINVAL (null pointer, n < 0, approx not 0/1, or another device
+ * current than the cover's), BM_EHIP. */
+int map_points_cover(const bm_cover* cover, const int32_t* xy, int64_t n, int32_t* out_ids, int32_t approx,
+                     hipStream_t stream);
+
 /* Error text for the last failing call on this thread ("" if none). */
 const char* bm_last_error(void);
 

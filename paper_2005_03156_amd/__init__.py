@@ -53,6 +53,22 @@ class Tuning(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class CoverCfg(C.Structure):
+    _fields_ = [("cell_log2", C.c_int32), ("threads", C.c_int32)]
+
+
+class CoverInfo(C.Structure):
+    _fields_ = [("origin_x", C.c_int32), ("origin_y", C.c_int32), ("log2_side", C.c_int32),
+                ("trie_levels", C.c_int32), ("last_level_bits", C.c_int32), ("cell_log2", C.c_int32),
+                ("trie_entries", C.c_int64), ("interior_entries", C.c_int64), ("node_entries", C.c_int64),
+                ("boundary_cells", C.c_int64), ("empty_entries", C.c_int64), ("cell_leaves", C.c_int64),
+                ("device_bytes", C.c_int64), ("build_seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if k == "build_seconds" else int(getattr(self, k)))
+                for k, _ in self._fields_}
+
+
 class LaunchTimes(C.Structure):
     _fields_ = [("map_ms", C.c_double), ("sort_ms", C.c_double), ("map_launches", C.c_int32),
                 ("sort_launches", C.c_int32)]
@@ -116,6 +132,11 @@ _SIGS = {
     "bm_server_reset_stats": (C.c_int, [_P]),
     "bm_server_run_trace": (C.c_int, [_P, C.POINTER(Request), _I64, _P]),
     "bm_server_destroy": (None, [_P]),
+    "bm_cover_create": (C.c_int, [_P, C.POINTER(IndexDesc), C.POINTER(CoverCfg), C.POINTER(C.c_void_p)]),
+    "bm_cover_destroy": (None, [_P]),
+    "bm_cover_get_info": (C.c_int, [_P, C.POINTER(CoverInfo)]),
+    "bm_cover_build_file": (C.c_int, [C.POINTER(IndexDesc), C.POINTER(CoverCfg), C.c_char_p]),
+    "map_points_cover": (C.c_int, [_P, _P, _I64, _P, C.c_int32, _P]),
     "bm_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -239,6 +260,69 @@ def map_points(index: Index, xy, out=None, stream=None, tuning: Tuning | None = 
         _check(lib.map_points(index.handle, pxy, n, pout, s))
     else:
         _check(lib.map_points_tuned(index.handle, pxy, n, pout, C.byref(tuning), s))
+    return out
+
+
+def build_cover_file(path: str, vert_off, verts, n_groups=(), parents=(), cell_log2: int = 0,
+                     threads: int = 0) -> None:
+    """Build an index and its cell cover on the host only and write the cover
+    to a file (no GPU needed)."""
+    d, keep = _desc(vert_off, verts, n_groups, parents)
+    cfg = CoverCfg(cell_log2, threads)
+    _check(lib.bm_cover_build_file(C.byref(d), C.byref(cfg), os.fsencode(path)))
+    del keep
+
+
+class Cover:
+    """The cell cover (fast approach) of a resident index, built from the same
+    rings the index was built from; keeps the index alive."""
+
+    def __init__(self, index: Index, vert_off, verts, cell_log2: int = 0, threads: int = 0):
+        self._h = None
+        self.index = index
+        d, keep = _desc(vert_off, verts, (), ())
+        cfg = CoverCfg(cell_log2, threads)
+        h = C.c_void_p()
+        _check(lib.bm_cover_create(index.handle, C.byref(d), C.byref(cfg), C.byref(h)))
+        del keep
+        self._h = h
+
+    @classmethod
+    def from_geometry(cls, index: Index, g, cell_log2: int = 0, threads: int = 0) -> "Cover":
+        return cls(index, g.vert_off, g.verts, cell_log2, threads)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = CoverInfo()
+        _check(lib.bm_cover_get_info(self._h, C.byref(i)))
+        return i.as_dict()
+
+    def close(self) -> None:
+        h, self._h = self._h, None
+        if h:
+            lib.bm_cover_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def map_points_cover(cover: Cover, xy, out=None, approx: bool = False, stream=None):
+    """Block id (or -1) of every point through the cell cover; approx=True
+    answers boundary cells with their centre's block."""
+    import torch
+    n = xy.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=xy.device)
+    if out.shape[0] != n:
+        raise ValueError("out has the wrong length")
+    _check(lib.map_points_cover(cover.handle, _dev_ptr(xy, "int32", (2,)), n, _dev_ptr(out, "int32"),
+                                1 if approx else 0, _stream_handle(stream)))
     return out
 
 

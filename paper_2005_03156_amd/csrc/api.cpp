@@ -145,6 +145,53 @@ __attribute__((visibility("default"))) int map_points_tuned(const bm_index* inde
   BM_GUARD("map_points")
 }
 
+__attribute__((visibility("default"))) int bm_cover_create(const bm_index* index, const bm_index_desc* desc,
+                                                          const bm_cover_cfg* cfg, bm_cover** out) {
+  try {
+    if (index) {
+      const int rc = check_device(index, "bm_cover_create");
+      if (rc != BM_OK) return rc;
+    }
+    return cover_create(index, desc, cfg, out);
+  }
+  BM_GUARD("bm_cover_create")
+}
+
+__attribute__((visibility("default"))) void bm_cover_destroy(bm_cover* cover) { cover_destroy(cover); }
+
+__attribute__((visibility("default"))) int bm_cover_get_info(const bm_cover* cover, bm_cover_info* info) {
+  if (!cover || !info) return fail(BM_EINVAL, "bm_cover_get_info: null argument");
+  *info = cover_info(cover);
+  return BM_OK;
+}
+
+__attribute__((visibility("default"))) int bm_cover_build_file(const bm_index_desc* desc, const bm_cover_cfg* cfg,
+                                                              const char* path) {
+  try {
+    return cover_build_file(desc, cfg, path);
+  }
+  BM_GUARD("bm_cover_build_file")
+}
+
+__attribute__((visibility("default"))) int map_points_cover(const bm_cover* cover, const int32_t* xy, int64_t n,
+                                                           int32_t* out_ids, int32_t approx, hipStream_t stream) {
+  try {
+    if (!cover) return fail(BM_EINVAL, "map_points_cover: null cover");
+    if (n < 0) return fail(BM_EINVAL, "map_points_cover: n < 0");
+    if (approx != 0 && approx != 1) return fail(BM_EINVAL, "map_points_cover: approx must be 0 or 1");
+    if (n == 0) return BM_OK;
+    if (!xy || !out_ids) return fail(BM_EINVAL, "map_points_cover: null buffer");
+    const bm_index* index = cover_index(cover);
+    int rc = check_device(index, "map_points_cover");
+    if (rc != BM_OK) return rc;
+    hipError_t e = launch_cover(index->k, cover_view(cover), xy, n, out_ids, approx != 0, tuning_from(nullptr),
+                                index->num_cu, stream);
+    if (e != hipSuccess) return fail(BM_EHIP, std::string("map_points_cover: launch: ") + hipGetErrorString(e));
+    return BM_OK;
+  }
+  BM_GUARD("map_points_cover")
+}
+
 __attribute__((visibility("default"))) int map_points_timed(const bm_index* index, const int32_t* xy, int64_t n,
                                                            int32_t* out_ids, const bm_tuning* t, hipStream_t stream,
                                                            bm_launch_times* times) {

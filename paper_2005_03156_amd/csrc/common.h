@@ -69,6 +69,31 @@ struct KIndex {
   int4 root_box;              // union of the level-0 boxes
 };
 
+// Cell cover (cover.cpp): a radix trie over non-overlapping square cells of
+// the plane, origin (ox, oy), side 2^log_side. Trie level t consumes `bits`
+// quadtree levels (4, the last level last_bits), i.e. a node of 4^bits entries
+// indexed by (x digit | y digit << bits). An entry is an interior cell (tag 0,
+// payload = block index), a child node (tag 1, payload = the child's first
+// entry), a boundary cell (tag 2, payload = cell number) or empty (all ones:
+// outside every block).
+struct CoverShape {
+  int32_t ox, oy;
+  int32_t log_side;
+  int32_t n_levels;
+  int32_t last_bits;
+  int32_t cell_log2;  // side of the finest cells: log_side - 4 * (n_levels - 1) - last_bits
+};
+constexpr uint32_t kCoverInterior = 0u << 30, kCoverNode = 1u << 30, kCoverBoundary = 2u << 30;
+constexpr uint32_t kCoverEmpty = 0xFFFFFFFFu, kCoverPayload = (1u << 30) - 1;
+
+struct KCover {
+  const uint32_t* ent;        // trie entries, root node first
+  const uint32_t* cell_off;   // [cells + 1]: boundary cell c lists cell_leaf[cell_off[c] .. cell_off[c+1])
+  const uint32_t* cell_leaf;  // leaf positions in the index's leaf array
+  const int32_t* cell_rep;    // per boundary cell: the answer at its centre (approximate mode)
+  int32_t ox, oy, log_side, n_levels, last_bits;
+};
+
 // One batch of the batched form, as laid out in device memory (identical to
 // the public bm_batch).
 struct BatchEntry {
@@ -109,6 +134,20 @@ hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, 
                           long long* meta, const Tuning& t, int num_cu, hipStream_t stream);
 hipError_t launch_quantize(const double* lonlat, int64_t n, int32_t* xy, int num_cu,
                            hipStream_t stream);
+// Cover form: every point looked up in the cell trie; boundary cells resolved
+// by the crossing test over their listed blocks, or (approx) by the cell's
+// stored answer.
+hipError_t launch_cover(const KIndex& ix, const KCover& cv, const int32_t* xy, int64_t n, int32_t* out,
+                        bool approx, const Tuning& t, int num_cu, hipStream_t stream);
+
+// Cover construction and access (cover.cpp).
+int cover_create(const bm_index* index, const bm_index_desc* desc, const bm_cover_cfg* cfg, bm_cover** out);
+int cover_build_file(const bm_index_desc* desc, const bm_cover_cfg* cfg, const char* path);
+void cover_destroy(bm_cover* cv);
+const KCover& cover_view(const bm_cover* cv);
+const bm_index* cover_index(const bm_cover* cv);
+int cover_device(const bm_cover* cv);
+const bm_cover_info& cover_info(const bm_cover* cv);
 
 // Thread-local error text + code helper.
 int fail(int code, const std::string& msg);

@@ -19,24 +19,12 @@
 #include <thread>
 #include <vector>
 
-#include "common.h"
+#include "host_index.h"
 
 namespace bm {
 namespace {
 
 constexpr int kTableMinChildren = 6;  // below this a group's children are simply all tested
-
-struct HostIndex {
-  int32_t n_levels = 0, g0 = 0, leaf_base = 0, n_leaves = 0;
-  int4 root_child = {0, 0, -1, 0};
-  int4 root_box = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
-  int64_t n_verts = 0;
-  std::vector<GroupRec> grp;
-  std::vector<LeafRec> leaf;
-  std::vector<int4> ent;
-  std::vector<uint64_t> slot_mask;
-  std::vector<int32_t> parent;
-};
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 
@@ -137,6 +125,8 @@ void build_slabs(const int2* v, int64_t m, const int4& bx, std::vector<int4>& en
     for (int64_t b = b0; b <= b1; ++b) ent[e0 + fill[b]++] = make_int4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
   }
 }
+
+}  // namespace
 
 int build_host(const bm_index_desc* d, HostIndex& h) {
   if (!d) return fail(BM_EINVAL, "bm_index_create: null descriptor");
@@ -291,6 +281,8 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
 }
 
 // Device copy of v followed by `pad` zeroed elements.
+namespace {
+
 template <class T>
 int upload(bm_index* ix, const std::vector<T>& v, const T** dst, size_t pad = 0) {
   void* p = nullptr;
@@ -358,28 +350,6 @@ int make_device(HostIndex& h, bm_index** out) {
 
 // ---- flat file: magic, scalars, then the arrays
 constexpr char kMagic[8] = {'B', 'M', 'I', 'D', 'X', '0', '0', '2'};
-
-template <class T>
-bool write_vec(FILE* f, const std::vector<T>& v) {
-  const int64_t n = (int64_t)v.size();
-  return fwrite(&n, sizeof n, 1, f) == 1 && (n == 0 || fwrite(v.data(), sizeof(T), n, f) == (size_t)n);
-}
-
-template <class T>
-bool read_vec(FILE* f, std::vector<T>& v, int64_t max_n) {
-  int64_t n = 0;
-  if (fread(&n, sizeof n, 1, f) != 1 || n < 0 || n > max_n) return false;
-  v.resize(n);
-  return n == 0 || fread(v.data(), sizeof(T), n, f) == (size_t)n;
-}
-
-template <class T>
-int download(const T* src, int64_t n, std::vector<T>& v) {
-  v.resize(n);
-  if (n == 0) return BM_OK;
-  hipError_t e = hipMemcpy(v.data(), src, n * sizeof(T), hipMemcpyDeviceToHost);
-  return e == hipSuccess ? BM_OK : fail(BM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
-}
 
 int write_host(const HostIndex& h, const char* path) {
   FILE* f = fopen(path, "wb");
@@ -459,9 +429,7 @@ int index_create(const bm_index_desc* d, bm_index** out) {
 
 void index_destroy(bm_index* ix) { free_index(ix); }
 
-int index_save(const bm_index* ix, const char* path) {
-  if (!ix || !path) return fail(BM_EINVAL, "bm_index_save: null argument");
-  HostIndex h;
+int index_to_host(const bm_index* ix, HostIndex& h) {
   const KIndex& k = ix->k;
   int rc = BM_OK;
   if (rc == BM_OK) rc = download(k.grp, (int64_t)k.leaf_base, h.grp);
@@ -477,7 +445,14 @@ int index_save(const bm_index* ix, const char* path) {
   h.root_child = k.root_child;
   h.root_box = k.root_box;
   h.n_verts = ix->n_verts;
-  return write_host(h, path);
+  return BM_OK;
+}
+
+int index_save(const bm_index* ix, const char* path) {
+  if (!ix || !path) return fail(BM_EINVAL, "bm_index_save: null argument");
+  HostIndex h;
+  const int rc = index_to_host(ix, h);
+  return rc == BM_OK ? write_host(h, path) : rc;
 }
 
 int index_build_file(const bm_index_desc* d, const char* path) {

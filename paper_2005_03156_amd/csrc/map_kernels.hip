@@ -252,6 +252,58 @@ __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, c
   }
 }
 
+// Crossing-number test on the cnt (leaf, point) pairs of list `cur`, 64 pairs
+// per round; odd pairs atomic-min their block index into the point's slot of
+// S.best. A pair only needs the ring edges listed for the y-slab holding its
+// point (every pair passed the leaf's box test, so the point lies in the
+// ring's y-extent); that list is cut into chunks of kChunk edges and all
+// chunks of the round are dealt across the lanes. The edge list is padded at
+// its end, so a chunk's loads never leave it. All 64 lanes take part.
+template <int kChunkShift>
+__device__ __forceinline__ void pip_rounds(const KIndex& ix, WaveLds& S, const int lane, const int cur,
+                                           const unsigned cnt) {
+  constexpr int kChunk = 1 << kChunkShift;
+  for (unsigned r = 0; r < cnt; r += kWave) {
+    const unsigned q = r + lane;
+    const bool has = q < cnt;
+    unsigned first = 0, len = 0, bid = 0;
+    const unsigned it = has ? S.item[cur][q] : 0u;
+    const int pl = (int)(it & (kTile - 1));
+    if (has) slab_range(ix, (int)(it >> kSlotBits) - ix.leaf_base, S.pts[pl].y, first, len, bid);
+    const unsigned nch = (len + kChunk - 1) >> kChunkShift;
+    const unsigned incl = wave_incl_scan(nch, lane);
+    const unsigned start = incl - nch;
+    const unsigned total = __shfl(incl, kWave - 1);
+    S.pair[lane] = make_uint4(first, len, start, (unsigned)pl);
+    S.par[lane] = 0;
+    for (unsigned w = 0; w < total; w += kCapChunk) {
+      const unsigned a = max(start, w), b = min(start + nch, w + (unsigned)kCapChunk);
+      for (unsigned c = a; c < b; ++c) S.ch_q[c - w] = (unsigned char)lane;
+      wave_sync();
+      const unsigned nw = min((unsigned)kCapChunk, total - w);
+      for (unsigned c = lane; c < nw; c += kWave) {
+        const unsigned pq = S.ch_q[c];
+        const uint4 pr = S.pair[pq];
+        const unsigned k0 = (w + c - pr.z) << kChunkShift;
+        const unsigned ne = min((unsigned)kChunk, pr.y - k0);
+        const int4* e = ix.ent + (pr.x + k0);
+        int4 ev[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) ev[u] = e[u];
+        const int2 pp = S.pts[pr.w];
+        unsigned acc = 0;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+          acc ^= ((unsigned)u < ne) ? crosses(make_int2(ev[u].x, ev[u].y), make_int2(ev[u].z, ev[u].w), pp) : 0u;
+        if (acc) atomicXor(&S.par[pq], 1u);
+      }
+      wave_sync();
+    }
+    if (has && (S.par[lane] & 1u)) atomicMin(&S.best[pl], bid);
+    wave_sync();
+  }
+}
+
 // The whole path for one tile of up to kTile points (point j * 64 + lane on
 // lane `lane`); all 64 lanes of the wave take part. Writes the result of
 // point i < nvalid to out[i], or to out[perm[i]] when a permutation is given
@@ -263,7 +315,6 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
                                          const int2* __restrict__ xy, const int nvalid,
                                          int* __restrict__ out, const int* __restrict__ perm = nullptr,
                                          const long long nperm = 0) {
-  constexpr int kChunk = 1 << kChunkShift;
 #pragma unroll
   for (int j = 0; j < kTilePts; ++j) {
     const int i = j * kWave + lane;
@@ -305,51 +356,7 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
     wave_sync();
   }
 
-  // ---- crossing-number test on the (leaf, point) pairs of list `cur`, 64
-  // pairs per round. A pair only needs the ring edges listed for the y-slab
-  // holding its point (the pair passed the leaf's box test, so the point lies
-  // in the ring's y-extent); that list is cut into chunks of kChunk edges and
-  // all chunks of the round are dealt across the lanes. The edge list is
-  // padded at its end, so a chunk's loads never leave it.
-  for (unsigned r = 0; r < cnt; r += kWave) {
-    const unsigned q = r + lane;
-    const bool has = q < cnt;
-    unsigned first = 0, len = 0, bid = 0;
-    const unsigned it = has ? S.item[cur][q] : 0u;
-    const int pl = (int)(it & (kTile - 1));
-    if (has) slab_range(ix, (int)(it >> kSlotBits) - ix.leaf_base, S.pts[pl].y, first, len, bid);
-    const unsigned nch = (len + kChunk - 1) >> kChunkShift;
-    const unsigned incl = wave_incl_scan(nch, lane);
-    const unsigned start = incl - nch;
-    const unsigned total = __shfl(incl, kWave - 1);
-    S.pair[lane] = make_uint4(first, len, start, (unsigned)pl);
-    S.par[lane] = 0;
-    for (unsigned w = 0; w < total; w += kCapChunk) {
-      const unsigned a = max(start, w), b = min(start + nch, w + (unsigned)kCapChunk);
-      for (unsigned c = a; c < b; ++c) S.ch_q[c - w] = (unsigned char)lane;
-      wave_sync();
-      const unsigned nw = min((unsigned)kCapChunk, total - w);
-      for (unsigned c = lane; c < nw; c += kWave) {
-        const unsigned pq = S.ch_q[c];
-        const uint4 pr = S.pair[pq];
-        const unsigned k0 = (w + c - pr.z) << kChunkShift;
-        const unsigned ne = min((unsigned)kChunk, pr.y - k0);
-        const int4* e = ix.ent + (pr.x + k0);
-        int4 ev[kChunk];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u) ev[u] = e[u];
-        const int2 pp = S.pts[pr.w];
-        unsigned acc = 0;
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-          acc ^= ((unsigned)u < ne) ? crosses(make_int2(ev[u].x, ev[u].y), make_int2(ev[u].z, ev[u].w), pp) : 0u;
-        if (acc) atomicXor(&S.par[pq], 1u);
-      }
-      wave_sync();
-    }
-    if (has && (S.par[lane] & 1u)) atomicMin(&S.best[pl], bid);
-    wave_sync();
-  }
+  pip_rounds<kChunkShift>(ix, S, lane, cur, cnt);
 
 #pragma unroll
   for (int j = 0; j < kTilePts; ++j) {
@@ -364,6 +371,94 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
     }
   }
   wave_sync();
+}
+
+// ---- cell cover (the fast approach) -------------------------------------
+// The trie entry of the cell holding p: interior (block index), boundary
+// (cell number) or kCoverEmpty (also for points off the covered square).
+__device__ __forceinline__ uint32_t cover_lookup(const KCover& cv, const int2 p) {
+  if (p.x < cv.ox || p.y < cv.oy) return kCoverEmpty;
+  const unsigned dx = (unsigned)p.x - (unsigned)cv.ox, dy = (unsigned)p.y - (unsigned)cv.oy;
+  if (((dx | dy) >> cv.log_side) != 0u) return kCoverEmpty;
+  int shift = cv.log_side;
+  unsigned node = 0;
+  for (int t = 0; t < cv.n_levels; ++t) {
+    const int bits = t == cv.n_levels - 1 ? cv.last_bits : 4;
+    shift -= bits;
+    const unsigned m = (1u << bits) - 1u;
+    const uint32_t v = cv.ent[node + (((dx >> shift) & m) | (((dy >> shift) & m) << bits))];
+    if ((v >> 30) != 1u) return v;
+    node = v & kCoverPayload;
+  }
+  return kCoverEmpty;  // the last trie level holds no node entries
+}
+
+// One tile through the cover: a point in an interior or empty cell takes the
+// trie's answer; a point in a boundary cell takes the cell's centre answer
+// (approx) or becomes a (leaf, point) pair for every listed block whose box
+// holds it, resolved by the same crossing-test rounds as the plain path.
+template <int kChunkShift>
+__device__ __forceinline__ void cover_tile(const KIndex& ix, const KCover& cv, WaveLds& S, const int lane,
+                                           const int2* __restrict__ xy, const int nvalid, int* __restrict__ out,
+                                           const bool approx) {
+#pragma unroll
+  for (int j = 0; j < kTilePts; ++j) {
+    const int i = j * kWave + lane;
+    S.pts[i] = i < nvalid ? xy[i] : make_int2(0, 0);
+    S.best[i] = 0xFFFFFFFFu;
+    S.ovf[i] = 0;
+  }
+  wave_sync();
+  unsigned cnt = 0;
+#pragma unroll
+  for (int j = 0; j < kTilePts; ++j) {
+    const int i = j * kWave + lane;
+    const int2 p = S.pts[i];
+    const uint32_t v = i < nvalid ? cover_lookup(cv, p) : kCoverEmpty;
+    const uint32_t tag = v >> 30, pay = v & kCoverPayload;
+    if (tag == 0u) S.best[i] = pay;
+    if (tag == 2u && approx) S.best[i] = (unsigned)cv.cell_rep[pay];
+    unsigned k = 0, k1 = 0;
+    if (tag == 2u && !approx) {
+      k = cv.cell_off[pay];
+      k1 = cv.cell_off[pay + 1];
+    }
+    for (; wave_any(k < k1); ++k) {
+      const bool h = k < k1;
+      const unsigned leaf = h ? cv.cell_leaf[k] : 0u;  // lanes without one read leaf 0
+      const int4 bx = ix.leaf[leaf].box;
+      emit(S, 0, h && in_box(bx, p), (unsigned)ix.leaf_base + leaf, i, cnt);
+    }
+  }
+  cnt = min(cnt, (unsigned)kCap);
+  wave_sync();
+  pip_rounds<kChunkShift>(ix, S, lane, 0, cnt);
+#pragma unroll
+  for (int j = 0; j < kTilePts; ++j) {
+    const int i = j * kWave + lane;
+    if (i < nvalid) {
+      unsigned best = S.best[i];
+      if (S.ovf[i]) best = min(best, walk_point(ix, S.pts[i]));
+      out[i] = (int)best;
+    }
+  }
+  wave_sync();
+}
+
+template <int kChunkShift>
+__global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void cover_map_kernel(
+    const KIndex ix, const KCover cv, const int2* __restrict__ xy, const long long n, int* __restrict__ out,
+    const int approx) {
+  __shared__ WaveLds wl[kWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  WaveLds& S = wl[threadIdx.x / kWave];
+  const long long ntiles = (n + kTile - 1) / kTile;
+  const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
+  for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
+       t += nwaves) {
+    const long long i0 = t * kTile;
+    cover_tile<kChunkShift>(ix, cv, S, lane, xy + i0, (int)min((long long)kTile, n - i0), out + i0, approx != 0);
+  }
 }
 
 // Plain form: the waves of the grid stride over the tiles.
@@ -703,6 +798,24 @@ hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, 
     case 4: launch_batch_map<2>(ix, tab, meta, t, num_cu, stream); break;
     case 16: launch_batch_map<4>(ix, tab, meta, t, num_cu, stream); break;
     default: launch_batch_map<3>(ix, tab, meta, t, num_cu, stream); break;
+  }
+  return hipGetLastError();
+}
+
+template <int kShift>
+static void launch_cover_t(const KIndex& ix, const KCover& cv, const int2* p, long long n, int* out, bool approx,
+                           const Tuning& t, int num_cu, hipStream_t stream) {
+  const dim3 grid((unsigned)grid_blocks<cover_map_kernel<kShift>>(n, t, num_cu));
+  hipLaunchKernelGGL(cover_map_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, cv, p, n, out, approx ? 1 : 0);
+}
+
+hipError_t launch_cover(const KIndex& ix, const KCover& cv, const int32_t* xy, int64_t n, int32_t* out, bool approx,
+                        const Tuning& t, int num_cu, hipStream_t stream) {
+  const int2* p = reinterpret_cast<const int2*>(xy);
+  switch (t.edge_chunk) {
+    case 8: launch_cover_t<3>(ix, cv, p, n, out, approx, t, num_cu, stream); break;
+    case 16: launch_cover_t<4>(ix, cv, p, n, out, approx, t, num_cu, stream); break;
+    default: launch_cover_t<2>(ix, cv, p, n, out, approx, t, num_cu, stream); break;
   }
   return hipGetLastError();
 }
