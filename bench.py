@@ -177,6 +177,7 @@ def main():
     }
     if not args.no_cover:
         res["cover"] = bench_cover(bm, torch, g, ix, xy, out, args.steps)
+    res["count_per_block"] = bench_count(bm, torch, out, g.n_blocks, args.steps)
     del xy, out
     torch.cuda.empty_cache()
     if not args.no_batched:
@@ -228,6 +229,27 @@ def bench_cover(bm, torch, g, ix, xy, ref, steps):
             (mode, wall * 1e3, n / wall, same))
     cv.close()
     return r
+
+
+def bench_count(bm, torch, ids, n_blocks, steps):
+    """Points per block over the plain path's 100M ids (the aggregation the
+    mapping feeds), checked against torch's bincount."""
+    counts = torch.zeros(n_blocks + 1, dtype=torch.int64, device=ids.device)
+    bm.count_per_block(ids, n_blocks, counts)
+    torch.cuda.synchronize()
+    ref = torch.bincount(torch.where(ids >= 0, ids, torch.full_like(ids, n_blocks)).long(),
+                         minlength=n_blocks + 1)
+    ok = bool(torch.equal(counts, ref))
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        bm.count_per_block(ids, n_blocks, counts, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    log("count per block: %.3f ms per 100M ids (%.3g ids/s), equal to bincount: %s" % (ms, ids.shape[0] / ms * 1e3, ok))
+    return {"ms": ms, "ids_per_s": ids.shape[0] / ms * 1e3, "equal_to_bincount": ok}
 
 
 def bench_batched(bm, torch, g, ix, nb=10_000):

@@ -391,6 +391,15 @@ int bm_cover_build_file(const bm_index_desc* desc, const bm_cover_cfg* cfg, cons
 int map_points_cover(const bm_cover* cover, const int32_t* xy, int64_t n, int32_t* out_ids, int32_t approx,
                      hipStream_t stream);
 
+/* Points per block: the count the mapping feeds into the paper's purpose,
+ * merging demographic data by block (Sec. I-II). For ids[0..n) (device, as
+ * written by map_points), adds to counts[b] (device, n_blocks + 1 uint64) the
+ * number of ids equal to b, for b in [0, n_blocks), and to counts[n_blocks]
+ * the number of the others (-1: no block). Counts accumulate: clear them first
+ * for a fresh count. Asynchronous on `stream`.
+ * Errors: BM_EINVAL (null buffer, n < 0, n_blocks outside [0, 2^31 - 2]), BM_EHIP. */
+int bm_count_per_block(const int32_t* ids, int64_t n, int64_t n_blocks, uint64_t* counts, hipStream_t stream);
+
 /* Error text for the last failing call on this thread ("" if none). */
 const char* bm_last_error(void);
 

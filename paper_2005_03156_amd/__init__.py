@@ -137,6 +137,7 @@ _SIGS = {
     "bm_cover_get_info": (C.c_int, [_P, C.POINTER(CoverInfo)]),
     "bm_cover_build_file": (C.c_int, [C.POINTER(IndexDesc), C.POINTER(CoverCfg), C.c_char_p]),
     "map_points_cover": (C.c_int, [_P, _P, _I64, _P, C.c_int32, _P]),
+    "bm_count_per_block": (C.c_int, [_P, _I64, _I64, _P, _P]),
     "bm_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -324,6 +325,29 @@ def map_points_cover(cover: Cover, xy, out=None, approx: bool = False, stream=No
     _check(lib.map_points_cover(cover.handle, _dev_ptr(xy, "int32", (2,)), n, _dev_ptr(out, "int32"),
                                 1 if approx else 0, _stream_handle(stream)))
     return out
+
+
+def count_per_block(ids, n_blocks: int, counts=None, stream=None):
+    """Points per block from a CUDA int32 id tensor: a uint64 tensor (as int64)
+    of n_blocks + 1 counts, the last one for ids outside [0, n_blocks).
+    Accumulates into `counts` when one is given."""
+    import torch
+    if counts is None:
+        counts = torch.zeros(n_blocks + 1, dtype=torch.int64, device=ids.device)
+    if counts.shape[0] != n_blocks + 1:
+        raise ValueError("counts must hold n_blocks + 1 entries")
+    _check(lib.bm_count_per_block(_dev_ptr(ids, "int32"), ids.shape[0], n_blocks, _dev_ptr(counts, "int64"),
+                                  _stream_handle(stream)))
+    return counts
+
+
+def join_per_block(counts, table):
+    """Host join of per-block counts with a per-block attribute table (e.g. the
+    blocks' FIPS codes or demographic columns, indexed by block): rows of
+    (attribute, count) for the blocks with at least one point."""
+    c = counts[:-1].cpu().numpy() if hasattr(counts, "cpu") else np.asarray(counts)[:-1]
+    nz = np.nonzero(c)[0]
+    return np.asarray(table)[nz], c[nz]
 
 
 def map_points_timed(index: Index, xy, out, stream=None, tuning: Tuning | None = None) -> dict:

@@ -1,6 +1,8 @@
 // C-ABI entry points of libblockmap: argument checks, error text, launches.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
+#include <climits>
 #include <exception>
 #include <new>
 #include <string>
@@ -190,6 +192,23 @@ __attribute__((visibility("default"))) int map_points_cover(const bm_cover* cove
     return BM_OK;
   }
   BM_GUARD("map_points_cover")
+}
+
+__attribute__((visibility("default"))) int bm_count_per_block(const int32_t* ids, int64_t n, int64_t n_blocks,
+                                                             uint64_t* counts, hipStream_t stream) {
+  try {
+    if (n < 0 || n_blocks < 0 || n_blocks > INT32_MAX - 1) return fail(BM_EINVAL, "bm_count_per_block: bad size");
+    if (!counts || (n > 0 && !ids)) return fail(BM_EINVAL, "bm_count_per_block: null buffer");
+    if (n == 0) return BM_OK;
+    int dev = 0, num_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = launch_count(ids, n, (int32_t)n_blocks, reinterpret_cast<unsigned long long*>(counts),
+                                std::max(1, num_cu), stream);
+    if (e != hipSuccess) return fail(BM_EHIP, std::string("bm_count_per_block: launch: ") + hipGetErrorString(e));
+    return BM_OK;
+  }
+  BM_GUARD("bm_count_per_block")
 }
 
 __attribute__((visibility("default"))) int map_points_timed(const bm_index* index, const int32_t* xy, int64_t n,

@@ -664,6 +664,35 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void map_sorte
   }
 }
 
+// Points per block: counts[b] += |{i : ids[i] == b}| for b < nb, and
+// counts[nb] += the ids outside [0, nb) (-1: no block). Lanes holding the same
+// id add it with one atomic (up to kAggRounds distinct ids per wave step;
+// the rest add one by one), which matters when points of one block arrive
+// together.
+constexpr int kAggRounds = 4;
+
+__global__ __launch_bounds__(256) void count_kernel(const int* __restrict__ ids, const long long n, const int nb,
+                                                    unsigned long long* __restrict__ counts) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const long long i = base + threadIdx.x;
+    bool active = i < n;
+    const int id = active ? ids[i] : -1;
+    const unsigned b = (id >= 0 && id < nb) ? (unsigned)id : (unsigned)nb;
+    for (int r = 0; r < kAggRounds; ++r) {
+      const unsigned long long act = __ballot(active);
+      if (act == 0ull) break;
+      const int leader = __builtin_ctzll(act);
+      const unsigned bl = __shfl(b, leader);
+      const unsigned long long same = __ballot(active && b == bl);
+      if (lane == leader) atomicAdd(&counts[bl], (unsigned long long)__popcll(same));
+      if (b == bl) active = false;
+    }
+    if (active) atomicAdd(&counts[b], 1ull);
+  }
+}
+
 // Quantiser: q = rint(v * 2^22) + 2^30 per axis; invalid input -> (-1, -1).
 // The product by a power of two is exact, so rint is the only rounding.
 __global__ __launch_bounds__(256) void quantize_kernel(const double2* __restrict__ ll,
@@ -817,6 +846,16 @@ hipError_t launch_cover(const KIndex& ix, const KCover& cv, const int32_t* xy, i
     case 16: launch_cover_t<4>(ix, cv, p, n, out, approx, t, num_cu, stream); break;
     default: launch_cover_t<2>(ix, cv, p, n, out, approx, t, num_cu, stream); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const int32_t* ids, int64_t n, int32_t nb, unsigned long long* counts, int num_cu,
+                        hipStream_t stream) {
+  long long blocks = (n + 255) / 256;
+  const long long cap = (long long)num_cu * 16;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(count_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, ids, (long long)n, nb, counts);
   return hipGetLastError();
 }
 

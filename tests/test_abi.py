@@ -108,3 +108,17 @@ def test_product_package_does_not_reference_the_oracle():
             if fn.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in txt.lower().replace("oracle-free", ""), fn
+
+
+def test_count_and_cover_argument_checks():
+    """Bad sizes and null buffers are refused before any device work."""
+    import paper_2005_03156_amd as bm
+    lib = bm.lib
+    assert lib.bm_count_per_block(None, -1, 10, None, None) == bm.BM_EINVAL
+    assert lib.bm_count_per_block(None, 5, 10, None, None) == bm.BM_EINVAL
+    assert lib.bm_count_per_block(None, 0, -3, None, None) == bm.BM_EINVAL
+    assert lib.map_points_cover(None, None, 10, None, 0, None) == bm.BM_EINVAL
+    assert lib.bm_cover_create(None, None, None, None) == bm.BM_EINVAL
+    assert lib.bm_cover_get_info(None, None) == bm.BM_EINVAL
+    lib.bm_cover_destroy(None)
+    assert b"cover" in lib.bm_last_error()

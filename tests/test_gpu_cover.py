@@ -177,3 +177,27 @@ def test_cover_ragged_sizes_and_errors(torch_cuda, bm):
     rc = bm.lib.map_points_cover(cv.handle, C.c_void_p(xy.data_ptr()), len(pts), C.c_void_p(out.data_ptr()), 2,
                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == bm.BM_EINVAL
+
+
+def test_count_per_block(torch_cuda, bm):
+    """Points per block equal numpy's bincount of the ids (the last slot for
+    ids outside [0, n_blocks)); counts accumulate over calls."""
+    torch = torch_cuda
+    g = synth.geometry(1)
+    ix = bm.Index.from_geometry(g)
+    pts = synth.points(1, 100_000)
+    ids = bm.map_points(ix, torch.from_numpy(pts).cuda())
+    rng = np.random.default_rng(2)
+    odd = torch.from_numpy(rng.choice(np.array([-1, -7, g.n_blocks, 2**31 - 1, 0, 5], np.int32), 3000)).cuda()
+    for name, t in [("mapped", ids), ("sorted", torch.sort(ids).values), ("odd", odd),
+                    ("ragged", ids[:777]), ("empty", ids[:0])]:
+        say("count per block", name)
+        got = bm.count_per_block(t, g.n_blocks).cpu().numpy()
+        a = t.cpu().numpy().astype(np.int64)
+        a = np.where((a >= 0) & (a < g.n_blocks), a, g.n_blocks)
+        assert np.array_equal(got, np.bincount(a, minlength=g.n_blocks + 1)), name
+    c = bm.count_per_block(ids, g.n_blocks)
+    bm.count_per_block(ids, g.n_blocks, counts=c)
+    assert np.array_equal(c.cpu().numpy(), 2 * bm.count_per_block(ids, g.n_blocks).cpu().numpy())
+    names, cnt = bm.join_per_block(c, np.array(["b%d" % b for b in range(g.n_blocks)]))
+    assert cnt.sum() == 2 * int((ids.cpu().numpy() >= 0).sum()) and len(names) == len(cnt)
