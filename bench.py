@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--no-cover", action="store_true", help="skip the cell-cover (fast approach) leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--served-requests", type=int, default=20_000)
-    ap.add_argument("--config3", action="store_true",
+    ap.add_argument("--quadtree8m", action="store_true",
                     help="also measure the 8M-block graded mesh streamed over 1B points (stderr)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -85,9 +85,9 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     t0 = time.time()
-    g = synth.geometry(2)
-    n = synth.CONFIGS[2]["n_points"]
-    pts = synth.points(2, n)
+    g = synth.geometry("grid221k")
+    n = synth.n_points("grid221k")
+    pts = synth.points("grid221k", n)
     log("generated %d blocks, %d points in %.1fs" % (g.n_blocks, n, time.time() - t0))
     ix = bm.Index.from_geometry(g)
     xy = torch.from_numpy(pts).to(dev)
@@ -182,11 +182,11 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         res["batched"] = bench_batched(bm, torch, g, ix)
-    if args.config3 or not args.no_served:
-        g3 = synth.geometry(3)
+    if args.quadtree8m or not args.no_served:
+        g3 = synth.geometry("quadtree8m")
         ix3 = bm.Index.from_geometry(g3)
-        if args.config3:
-            res["config3"] = bench_config3(bm, torch, g3, ix3)
+        if args.quadtree8m:
+            res["quadtree8m"] = bench_quadtree8m(bm, torch, g3, ix3)
         if not args.no_served:
             res["served"] = bench_served(bm, torch, g3, ix3, args.served_requests)
         ix3.close()
@@ -258,13 +258,13 @@ def bench_batched(bm, torch, g, ix, nb=10_000):
     log-uniform on [0.1%, 5%] of the extent). One graph replay (and one eager
     persistent launch) against one plain launch per batch."""
     t0 = time.time()
-    sizes = synth.sizes(synth.key(4, 2, 0), nb, 0, 0.0, 0.0, 1e6)
+    sizes = synth.sizes(synth.key("batches10k", 2, 0), nb, 0, 0.0, 0.0, 1e6)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     total = int(off[-1])
     host = np.empty((total, 2), np.int32)
     for b in range(nb):
-        m = synth.Mixture(synth.key(4, 2, b + 1), 1, g.W, 0.0, 0.001, 0.05, 0.0)
-        m.sample(synth.key(4, 3, b + 1), 0, int(sizes[b]), out=host[off[b]:off[b + 1]])
+        m = synth.Mixture(synth.key("batches10k", 2, b + 1), 1, g.W, 0.0, 0.001, 0.05, 0.0)
+        m.sample(synth.key("batches10k", 3, b + 1), 0, int(sizes[b]), out=host[off[b]:off[b + 1]])
     xy = torch.from_numpy(host).cuda()
     del host
     out = torch.empty(total, dtype=torch.int32, device="cuda")
@@ -344,12 +344,12 @@ def bench_served(bm, torch, g, ix, nreq):
     baseline's capacity, and all at once."""
     t0 = time.time()
     npool = 1000
-    sizes = synth.sizes(synth.key(5, 2, 0), npool, 1, 10_000.0, 2.0, 10_000_000)
+    sizes = synth.sizes(synth.key("requests20k", 2, 0), npool, 1, 10_000.0, 2.0, 10_000_000)
     pool, outs, ref = [], [], []
     for r in range(npool):
-        m = synth.Mixture(synth.key(5, 2, r + 1), 1, g.W, 0.0, 0.001, 0.02, 0.2)
+        m = synth.Mixture(synth.key("requests20k", 2, r + 1), 1, g.W, 0.0, 0.001, 0.02, 0.2)
         x = torch.empty((int(sizes[r]), 2), dtype=torch.int32, pin_memory=True).numpy()
-        m.sample(synth.key(5, 3, r + 1), 0, int(sizes[r]), out=x)
+        m.sample(synth.key("requests20k", 3, r + 1), 0, int(sizes[r]), out=x)
         pool.append(x)
         outs.append(torch.empty(int(sizes[r]), dtype=torch.int32, pin_memory=True).numpy())
         ref.append(bm.map_points(ix, torch.from_numpy(x).cuda()).cpu().numpy())
@@ -397,7 +397,7 @@ def bench_served(bm, torch, g, ix, nreq):
     return res
 
 
-def bench_config3(bm, torch, g, ix):
+def bench_quadtree8m(bm, torch, g, ix):
     """8M blocks, 1B points streamed in 2^26-point chunks from pinned host
     memory: kernel-only rate (chunk resident) and end-to-end rate with the
     copies overlapped on a second stream."""
@@ -410,8 +410,8 @@ def bench_config3(bm, torch, g, ix):
     hout = [torch.empty(CH, dtype=torch.int32, pin_memory=True) for _ in range(2)]
     dxy = [torch.empty((CH, 2), dtype=torch.int32, device="cuda") for _ in range(2)]
     dout = [torch.empty(CH, dtype=torch.int32, device="cuda") for _ in range(2)]
-    synth.points(3, CH, 0, out=host[0].numpy())
-    log("config3: %d blocks, %.2f GB index, generated in %.1fs" % (g.n_blocks, info["device_bytes"] / 1e9,
+    synth.points("quadtree8m", CH, 0, out=host[0].numpy())
+    log("quadtree8m: %d blocks, %.2f GB index, generated in %.1fs" % (g.n_blocks, info["device_bytes"] / 1e9,
                                                                    time.time() - t0))
     # kernel only: chunk 0 resident
     dxy[0].copy_(host[0])
@@ -433,7 +433,7 @@ def bench_config3(bm, torch, g, ix):
         n = min(CH, N - k * CH)
         b = k & 1
         torch.cuda.synchronize()
-        synth.points(3, n, k * CH, out=host[b][:n].numpy())
+        synth.points("quadtree8m", n, k * CH, out=host[b][:n].numpy())
         t = time.perf_counter()
         with torch.cuda.stream(copy):
             dxy[b][:n].copy_(host[b][:n], non_blocking=True)
@@ -445,7 +445,7 @@ def bench_config3(bm, torch, g, ix):
     res = {"blocks": g.n_blocks, "vertices": int(g.verts.shape[0]), "points": N,
            "kernel_points_per_s": CH / (kern_ms * 1e-3), "kernel_ms_per_chunk": kern_ms,
            "end_to_end_points_per_s": N / t_wall, "index_device_bytes": info["device_bytes"]}
-    log("config3: kernel %.3f ms per 2^26 chunk (%.3g pts/s); end-to-end with PCIe %.3g pts/s" %
+    log("quadtree8m: kernel %.3f ms per 2^26 chunk (%.3g pts/s); end-to-end with PCIe %.3g pts/s" %
         (kern_ms, res["kernel_points_per_s"], res["end_to_end_points_per_s"]))
     return res
 

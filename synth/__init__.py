@@ -76,8 +76,16 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def key(cfg: int, stream: int, k: int = 0) -> int:
-    return int(_L().syn_key(SEED, cfg, stream, k))
+# Each workload draws from its own seed stream (a small integer folded into
+# every key), so adding a workload never changes another one's data.
+SEED_STREAM = {"grid1k": 1, "grid221k": 2, "quadtree8m": 3, "batches10k": 4, "requests20k": 5}
+
+
+def key(workload, stream: int, k: int = 0) -> int:
+    """Counter-based key for (workload, stream, k); workload is a name of
+    SEED_STREAM (or its integer seed stream)."""
+    wid = SEED_STREAM[workload] if isinstance(workload, str) else int(workload)
+    return int(_L().syn_key(SEED, wid, stream, k))
 
 
 class _GridParams(C.Structure):
@@ -132,30 +140,38 @@ def band_hierarchy(n: int, bands):
     return [int(r * c) for r, c in bands], parents
 
 
-# ------------------------------------------------------------ the configs ----
+# ---------------------------------------------------------- the workloads ----
 
-# config 1: 32 x 32 jittered grid over [0, 1e6]^2, 3..6 points per shared edge,
-# 8 x 8 groups of 4 x 4 blocks; 100,000 points.
-# config 2: 470 x 470 grid (220,900 blocks), 2 + Geometric(1/4) (<= 40) points
+# grid1k: 32 x 32 jittered grid over [0, 1e6]^2 (1,024 blocks), 3..6 points per
+# shared edge, 8 x 8 groups of 4 x 4 blocks; 100,000 points.
+# grid221k: 470 x 470 grid (220,900 blocks), 2 + Geometric(1/4) (<= 40) points
 # per edge; 50 regions / 3,000 counties / 70,000 tracts; 100M points.
-CONFIGS = {
-    1: dict(n=32, c=31_250, klaw=0, kmin=3, kmax=6, kp=0.0, bands=[(8, 8)], n_points=100_000,
+# quadtree8m: the graded quadtree mesh below (about 8M blocks); 1B points.
+WORKLOADS = {
+    "grid1k": dict(n=32, c=31_250, klaw=0, kmin=3, kmax=6, kp=0.0, bands=[(8, 8)], n_points=100_000,
             K=5, wsig=0.0, sig=(0.05, 0.05), p_unif=0.20),
-    2: dict(n=470, c=2_000_000, klaw=1, kmin=2, kmax=40, kp=0.25,
+    "grid221k": dict(n=470, c=2_000_000, klaw=1, kmin=2, kmax=40, kp=0.25,
             bands=[(5, 10), (50, 60), (250, 280)], n_points=100_000_000,
             K=200, wsig=1.0, sig=(0.005, 0.05), p_unif=0.05),
 }
 
 
-def geometry(cfg: int) -> Geometry:
-    if cfg == 3:
+def geometry(workload: str) -> Geometry:
+    """The block partition and hierarchy of a workload ("grid1k", "grid221k",
+    "quadtree8m")."""
+    if workload == "quadtree8m":
         return quadtree_geometry(**QUADTREE)
-    p = CONFIGS[cfg]
+    p = WORKLOADS[workload]
     off, verts = jittered_grid(p["n"], p["c"], klaw=p["klaw"], kmin=p["kmin"], kmax=p["kmax"],
-                               kp=p["kp"], key_=key(cfg, 0, 0))
+                               kp=p["kp"], key_=key(workload, 0, 0))
     n_groups, parents = band_hierarchy(p["n"], p["bands"])
-    return Geometry(off, verts, n_groups, parents, W=p["n"] * p["c"], name="config%d" % cfg,
+    return Geometry(off, verts, n_groups, parents, W=p["n"] * p["c"], name=workload,
                     meta=dict(grid_n=p["n"], cell=p["c"]))
+
+
+def n_points(workload: str) -> int:
+    """Size of a workload's point stream."""
+    return QUADTREE["n_points"] if workload == "quadtree8m" else WORKLOADS[workload]["n_points"]
 
 
 class Mixture:
@@ -177,17 +193,17 @@ class Mixture:
         return out
 
 
-def points(cfg: int, n: int | None = None, i0: int = 0, out: np.ndarray | None = None) -> np.ndarray:
-    """Points i0 .. i0+n-1 of a config's point stream (int32 [n, 2])."""
-    if cfg == 3:
+def points(workload: str, n: int | None = None, i0: int = 0, out: np.ndarray | None = None) -> np.ndarray:
+    """Points i0 .. i0+n-1 of a workload's point stream (int32 [n, 2])."""
+    if workload == "quadtree8m":
         q = QUADTREE
         n = q["n_points"] if n is None else n
-        return quadtree_mixture(q).sample(key(3, 1, 1), i0, n, out)
-    p = CONFIGS[cfg]
+        return quadtree_mixture(q).sample(key(workload, 1, 1), i0, n, out)
+    p = WORKLOADS[workload]
     W = p["n"] * p["c"]
     n = p["n_points"] if n is None else n
-    m = Mixture(key(cfg, 1, 0), p["K"], W, p["wsig"], p["sig"][0], p["sig"][1], p["p_unif"])
-    return m.sample(key(cfg, 1, 1), i0, n, out)
+    m = Mixture(key(workload, 1, 0), p["K"], W, p["wsig"], p["sig"][0], p["sig"][1], p["p_unif"])
+    return m.sample(key(workload, 1, 1), i0, n, out)
 
 
 def sizes(key_: int, nb: int, law: int, median: float, s: float, hi: float) -> np.ndarray:
@@ -205,19 +221,19 @@ class _QtParams(C.Structure):
                 ("vmax", C.c_int32), ("key", C.c_uint64), ("factor", C.c_void_p)]
 
 
-# config 3: 2^30 square of 512 x 512 root cells, each cut into 4^d equal
+# quadtree8m: 2^30 square of 512 x 512 root cells, each cut into 4^d equal
 # leaves (d <= 5, neighbours differ by <= 1) following the point density, to
 # about 8M leaves; per-segment interior points from a Lomax(2) law (block
 # mean about 30, 4..2000 vertices); hierarchy 64 / 4,096 / 262,144 root cells
 # / depth-2 quadtree nodes / leaves; 1B points in chunks of 2^26.
 QUADTREE = dict(R=512, lg_cell=21, maxd=5, target_leaves=8_000_000, vjit=0.25, pjit=0.10, taper=0.2,
                 k_lambda=7.0, k_alpha=2.0, vmax=2000, K=64, wsig=1.0, sig=(0.002, 0.03), p_unif=0.03,
-                n_points=1_000_000_000, chunk=1 << 26, cfg=3)
+                n_points=1_000_000_000, chunk=1 << 26, workload="quadtree8m")
 
 
 def quadtree_mixture(q) -> Mixture:
     W = float(q["R"] << q["lg_cell"])
-    return Mixture(key(q["cfg"], 1, 0), q["K"], W, q["wsig"], q["sig"][0], q["sig"][1], q["p_unif"])
+    return Mixture(key(q["workload"], 1, 0), q["K"], W, q["wsig"], q["sig"][0], q["sig"][1], q["p_unif"])
 
 
 def _balance(d: np.ndarray) -> np.ndarray:
@@ -271,7 +287,7 @@ def quadtree_geometry(**q) -> Geometry:
     nl = int(leaf_off[-1])
     factor = np.empty(nl, np.float32)
     qp = _QtParams(R, q["lg_cell"], q["maxd"], depth.ctypes.data, leaf_off.ctypes.data, q["vjit"],
-                   q["pjit"], q["taper"], q["k_lambda"], q["k_alpha"], q["vmax"], key(q["cfg"], 0, 0),
+                   q["pjit"], q["taper"], q["k_lambda"], q["k_alpha"], q["vmax"], key(q["workload"], 0, 0),
                    factor.ctypes.data)
     off = np.empty(nl + 1, np.int64)
     total = _L().syn_qt_offsets(C.byref(qp), nl, _p(off))
@@ -288,5 +304,5 @@ def quadtree_geometry(**q) -> Geometry:
     t0 = (ty // 8) * (R // 64) + tx // 8
     parents = [t0.astype(np.int32), t1.astype(np.int32), group_cell, leaf_group]
     n_groups = [(R // 64) ** 2, (R // 8) ** 2, R * R, ng]
-    return Geometry(off, verts, n_groups, parents, W=R << q["lg_cell"], name="config3",
+    return Geometry(off, verts, n_groups, parents, W=R << q["lg_cell"], name="quadtree8m",
                     meta=dict(depth=depth.reshape(R, R), leaf_off=leaf_off))

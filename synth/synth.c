@@ -42,10 +42,10 @@ static inline double u01(uint64_t key, uint64_t i) {
   return (double)(rnd(key, i) >> 11) * (1.0 / 9007199254740992.0);
 }
 
-/* key of (seed, config, stream, index): streams 0 = geometry, 1 = points,
+/* key of (seed, workload seed stream, stream, index): streams 0 = geometry, 1 = points,
  * 2 = batches / requests; index = chunk, batch or request number */
-SYN_API uint64_t syn_key(uint64_t seed, uint64_t cfg, uint64_t stream, uint64_t k) {
-  return mix64(mix64(mix64(mix64(seed) ^ cfg) ^ (stream * 0x100000001B3ull)) ^ k);
+SYN_API uint64_t syn_key(uint64_t seed, uint64_t wid, uint64_t stream, uint64_t k) {
+  return mix64(mix64(mix64(mix64(seed) ^ wid) ^ (stream * 0x100000001B3ull)) ^ k);
 }
 
 SYN_API uint64_t syn_rand_u64(uint64_t key, uint64_t i) { return rnd(key, i); }

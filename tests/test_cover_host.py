@@ -113,17 +113,17 @@ def check_cover(g, cv, ix, xy):
 
 
 @pytest.fixture(scope="module")
-def cfg1_cover(tmp_path_factory):
+def grid1k_cover(tmp_path_factory):
     import paper_2005_03156_amd as bm
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     d = tmp_path_factory.mktemp("cov")
     bm.build_cover_file(str(d / "c1.bmc"), g.vert_off, g.verts, g.n_groups, g.parents)
     bm.build_index_file(str(d / "c1.bmi"), g.vert_off, g.verts, g.n_groups, g.parents)
     return g, read_cover(str(d / "c1.bmc")), read_index(str(d / "c1.bmi"))
 
 
-def test_structure(cfg1_cover):
-    g, cv, ix = cfg1_cover
+def test_structure(grid1k_cover):
+    g, cv, ix = grid1k_cover
     ent = cv["ent"]
     tag = np.where(ent == EMPTY, 3, ent >> 30)
     assert np.all(tag <= 3)
@@ -143,23 +143,23 @@ def test_structure(cfg1_cover):
     assert max(rb[1] - rb[0], rb[3] - rb[2]) <= 1 << cv["log_side"]
 
 
-def test_random_points(cfg1_cover):
-    g, cv, ix = cfg1_cover
-    xy = synth.points(1, 100_000)
+def test_random_points(grid1k_cover):
+    g, cv, ix = grid1k_cover
+    xy = synth.points("grid1k", 100_000)
     tag = check_cover(g, cv, ix, xy)
     # the cover does its job: most points need no crossing test
     assert np.mean(tag == 2) < 0.25
 
 
-def test_grid_and_vertex_points(cfg1_cover):
-    g, cv, ix = cfg1_cover
+def test_grid_and_vertex_points(grid1k_cover):
+    g, cv, ix = grid1k_cover
     rng = np.random.default_rng(5)
     check_cover(g, cv, ix, grid_points(cv, rng, 30_000))
     check_cover(g, cv, ix, vertex_points(g, rng, 30_000))
 
 
-def test_outside_points(cfg1_cover):
-    g, cv, ix = cfg1_cover
+def test_outside_points(grid1k_cover):
+    g, cv, ix = grid1k_cover
     xy = np.array([[-1, -1], [0, -5], [-7, 100], [2**31 - 1, 2**31 - 1], [cv["ox"] + (1 << cv["log_side"]), 0]],
                   np.int32)
     v, _ = walk(cv, xy)
@@ -171,13 +171,13 @@ def test_outside_points(cfg1_cover):
 def test_cell_sizes(tmp_path, cl):
     """A fine and a coarse finest side both give a correct cover."""
     import paper_2005_03156_amd as bm
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     bm.build_cover_file(str(tmp_path / "c.bmc"), g.vert_off, g.verts, g.n_groups, g.parents, cell_log2=cl)
     bm.build_index_file(str(tmp_path / "c.bmi"), g.vert_off, g.verts, g.n_groups, g.parents)
     cv, ix = read_cover(str(tmp_path / "c.bmc")), read_index(str(tmp_path / "c.bmi"))
     assert cv["cell_log2"] == cl
     rng = np.random.default_rng(cl)
-    check_cover(g, cv, ix, np.concatenate([synth.points(1, 20_000), grid_points(cv, rng, 10_000)]))
+    check_cover(g, cv, ix, np.concatenate([synth.points("grid1k", 20_000), grid_points(cv, rng, 10_000)]))
 
 
 def test_overlapping_blocks(tmp_path):
@@ -209,7 +209,7 @@ def test_overlapping_blocks(tmp_path):
 
 def test_bad_config(tmp_path):
     import paper_2005_03156_amd as bm
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     with pytest.raises(bm.BlockmapError):
         bm.build_cover_file(str(tmp_path / "x.bmc"), g.vert_off, g.verts, cell_log2=31)
     with pytest.raises(bm.BlockmapError):

@@ -66,16 +66,16 @@ def check(bm, torch, cv, pts, exact_fn, approx_sample=None):
     return got, apx
 
 
-def test_cover_config1_exact_and_approx(torch_cuda, bm):
-    say("cover config1")
-    g = synth.geometry(1)
+def test_cover_grid1k_exact_and_approx(torch_cuda, bm):
+    say("cover grid1k")
+    g = synth.geometry("grid1k")
     ix = bm.Index.from_geometry(g)
     cv = bm.Cover.from_geometry(ix, g)
     info = cv.info()
     assert info["boundary_cells"] > 0 and info["interior_entries"] > 0 and info["device_bytes"] > 0
     rng = np.random.default_rng(3)
     out = np.array([[-1, -1], [-2**31, 5], [2**31 - 1, 2**31 - 1], [0, 2**31 - 1], [5, -7]], np.int32)
-    pts = np.concatenate([synth.points(1), boundary_points(g), grid_points(info, rng, 30_000), out])
+    pts = np.concatenate([synth.points("grid1k"), boundary_points(g), grid_points(info, rng, 30_000), out])
     got, apx = check(bm, torch_cuda, cv, pts, lambda p: oracle.brute(g.vert_off, g.verts, p, box_reject=True))
     assert (got == -1).any() and (got >= 0).any()
     assert (apx != got).any()  # points in boundary cells really are answered from the cell
@@ -87,24 +87,24 @@ def test_cover_config1_exact_and_approx(torch_cuda, bm):
 @pytest.mark.parametrize("cl", [7, 13])
 def test_cover_cell_sizes(torch_cuda, bm, cl):
     say("cover cell size", cl)
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     ix = bm.Index.from_geometry(g)
     cv = bm.Cover.from_geometry(ix, g, cell_log2=cl)
     assert cv.info()["cell_log2"] == cl
     rng = np.random.default_rng(cl)
-    pts = np.concatenate([synth.points(1, 30_000), grid_points(cv.info(), rng, 10_000), boundary_points(g, 1000)])
+    pts = np.concatenate([synth.points("grid1k", 30_000), grid_points(cv.info(), rng, 10_000), boundary_points(g, 1000)])
     check(bm, torch_cuda, cv, pts, lambda p: oracle.brute(g.vert_off, g.verts, p, box_reject=True))
 
 
-def test_cover_config2_two_million(torch_cuda, bm):
-    say("cover config2: build")
-    g = synth.geometry(2)
+def test_cover_grid221k_two_million(torch_cuda, bm):
+    say("cover grid221k: build")
+    g = synth.geometry("grid221k")
     ix = bm.Index.from_geometry(g)
     cv = bm.Cover.from_geometry(ix, g)
     H = oracle.Hier.from_geometry(g)
-    say("cover config2:", cv.info())
+    say("cover grid221k:", cv.info())
     rng = np.random.default_rng(9)
-    pts = np.concatenate([synth.points(2, 2_000_000), boundary_points(g, 20_000, seed=4),
+    pts = np.concatenate([synth.points("grid221k", 2_000_000), boundary_points(g, 20_000, seed=4),
                           grid_points(cv.info(), rng, 50_000)])
     got, _ = check(bm, torch_cuda, cv, pts, H.map, approx_sample=300_000)
     xy = torch_cuda.from_numpy(pts).cuda()
@@ -157,10 +157,10 @@ def test_cover_heavy_ring(torch_cuda, bm):
 
 def test_cover_ragged_sizes_and_errors(torch_cuda, bm):
     torch = torch_cuda
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     ix = bm.Index.from_geometry(g)
     cv = bm.Cover.from_geometry(ix, g)
-    pts = synth.points(1, 5000, i0=777)
+    pts = synth.points("grid1k", 5000, i0=777)
     want = oracle.brute(g.vert_off, g.verts, pts)
     for n in [0, 1, 63, 64, 65, 127, 128, 129, 1000, 4097]:
         say("cover ragged", n)
@@ -183,9 +183,9 @@ def test_count_per_block(torch_cuda, bm):
     """Points per block equal numpy's bincount of the ids (the last slot for
     ids outside [0, n_blocks)); counts accumulate over calls."""
     torch = torch_cuda
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     ix = bm.Index.from_geometry(g)
-    pts = synth.points(1, 100_000)
+    pts = synth.points("grid1k", 100_000)
     ids = bm.map_points(ix, torch.from_numpy(pts).cuda())
     rng = np.random.default_rng(2)
     odd = torch.from_numpy(rng.choice(np.array([-1, -7, g.n_blocks, 2**31 - 1, 0, 5], np.int32), 3000)).cuda()

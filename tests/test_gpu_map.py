@@ -44,12 +44,12 @@ def boundary_points(g, k=3000, seed=0):
     return (v[:, None, :] + offs[None]).reshape(-1, 2).astype(np.int32)
 
 
-# ------------------------------------------------------------ config 1 ----
+# ------------------------------------------------------------ grid1k ----
 
-def test_config1_full_vs_brute_force(torch_cuda, bm):
-    say("config1: 100k points + boundary points vs brute force")
-    g = synth.geometry(1)
-    pts = np.concatenate([synth.points(1), boundary_points(g)])
+def test_grid1k_full_vs_brute_force(torch_cuda, bm):
+    say("grid1k: 100k points + boundary points vs brute force")
+    g = synth.geometry("grid1k")
+    pts = np.concatenate([synth.points("grid1k"), boundary_points(g)])
     ix = bm.Index.from_geometry(g)
     got = gpu_map(bm, torch_cuda, ix, pts)
     want = oracle.brute(g.vert_off, g.verts, pts)
@@ -60,9 +60,9 @@ def test_config1_full_vs_brute_force(torch_cuda, bm):
 @pytest.mark.parametrize("chunk", [4, 8, 16])
 @pytest.mark.parametrize("bpc", [1, 3])
 def test_launch_shape_never_changes_results(torch_cuda, bm, chunk, bpc):
-    say("config1 tuning", chunk, bpc)
-    g = synth.geometry(1)
-    pts = np.concatenate([synth.points(1, 30_001), boundary_points(g, 500)])
+    say("grid1k tuning", chunk, bpc)
+    g = synth.geometry("grid1k")
+    pts = np.concatenate([synth.points("grid1k", 30_001), boundary_points(g, 500)])
     ix = bm.Index.from_geometry(g)
     t = bm.Tuning(chunk, bpc, 65536)
     got = gpu_map(bm, torch_cuda, ix, pts, tuning=t)
@@ -71,9 +71,9 @@ def test_launch_shape_never_changes_results(torch_cuda, bm, chunk, bpc):
 
 
 def test_ragged_sizes_and_empty(torch_cuda, bm):
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     ix = bm.Index.from_geometry(g)
-    pts = synth.points(1, 5000)
+    pts = synth.points("grid1k", 5000)
     want = oracle.brute(g.vert_off, g.verts, pts)
     for n in [0, 1, 2, 63, 64, 65, 255, 257, 1000, 4999]:
         say("ragged n =", n)
@@ -83,7 +83,7 @@ def test_ragged_sizes_and_empty(torch_cuda, bm):
 
 def test_extreme_coordinates(torch_cuda, bm):
     say("extreme coordinates")
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     ix = bm.Index.from_geometry(g)
     I32 = np.iinfo(np.int32)
     vals = [I32.min, I32.min + 1, -1, 0, 1, g.W - 1, g.W, I32.max - 1, I32.max]
@@ -92,18 +92,18 @@ def test_extreme_coordinates(torch_cuda, bm):
     assert (got == oracle.brute(g.vert_off, g.verts, pts)).all()
 
 
-# ------------------------------------------------------------ config 2 ----
+# ------------------------------------------------------------ grid221k ----
 
 @pytest.fixture(scope="module")
-def cfg2(bm, torch_cuda):
-    g = synth.geometry(2)
+def grid221k(bm, torch_cuda):
+    g = synth.geometry("grid221k")
     return g, bm.Index.from_geometry(g), oracle.Hier.from_geometry(g)
 
 
-def test_config2_two_million_vs_hierarchy_oracle(torch_cuda, bm, cfg2):
-    say("config2: 2M points vs hierarchy oracle; sample vs brute force")
-    g, ix, H = cfg2
-    pts = np.concatenate([synth.points(2, 2_000_000), boundary_points(g, 20_000, seed=3)])
+def test_grid221k_two_million_vs_hierarchy_oracle(torch_cuda, bm, grid221k):
+    say("grid221k: 2M points vs hierarchy oracle; sample vs brute force")
+    g, ix, H = grid221k
+    pts = np.concatenate([synth.points("grid221k", 2_000_000), boundary_points(g, 20_000, seed=3)])
     got = gpu_map(bm, torch_cuda, ix, pts)
     want = H.map(pts)
     assert (got == want).all(), int((got != want).sum())
@@ -111,13 +111,13 @@ def test_config2_two_million_vs_hierarchy_oracle(torch_cuda, bm, cfg2):
     assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all()
 
 
-def test_spatial_presort_never_changes_results(torch_cuda, bm, cfg2):
+def test_spatial_presort_never_changes_results(torch_cuda, bm, grid221k):
     """Calls above the pre-sort threshold, sorted or not, several chunks with
     a ragged tail: identical outputs, equal to the oracle on a sample."""
     torch = torch_cuda
-    g, ix, H = cfg2
+    g, ix, H = grid221k
     n = 3 * (1 << 22) + 12345
-    pts = synth.points(2, n, i0=5_000_000)
+    pts = synth.points("grid221k", n, i0=5_000_000)
     xy = torch.from_numpy(pts).cuda()
     say("presort on/off", n)
     a = bm.map_points(ix, xy, tuning=bm.Tuning(4, 5, 2048, 1))
@@ -128,20 +128,20 @@ def test_spatial_presort_never_changes_results(torch_cuda, bm, cfg2):
     assert (a.cpu().numpy()[sub] == H.map(pts[sub])).all()
 
 
-def test_config2_full_size_sampled_and_partition_property(torch_cuda, bm, cfg2):
+def test_grid221k_full_size_sampled_and_partition_property(torch_cuda, bm, grid221k):
     """100M points in the benchmark's launch shape: sampled outputs against the
     oracle, and at every point the partition property (an id exactly when the
     point lies in [0, W)^2)."""
     torch = torch_cuda
-    g, ix, H = cfg2
-    n = synth.CONFIGS[2]["n_points"]
-    say("config2 full size: generating", n)
-    pts = synth.points(2, n)
+    g, ix, H = grid221k
+    n = synth.n_points("grid221k")
+    say("grid221k full size: generating", n)
+    pts = synth.points("grid221k", n)
     xy = torch.from_numpy(pts).cuda()
     out = bm.map_points(ix, xy)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    say("config2 full size: checking")
+    say("grid221k full size: checking")
     x, y = pts[:, 0], pts[:, 1]
     inside = (x >= 0) & (x < g.W) & (y >= 0) & (y < g.W)
     assert ((got >= 0) == inside).all()
@@ -196,8 +196,8 @@ def test_heavy_ring_and_many_small(torch_cuda, bm):
 
 
 def test_random_hierarchies_and_empty_groups(torch_cuda, bm):
-    g = synth.geometry(1)
-    pts = np.concatenate([synth.points(1, 20000), boundary_points(g, 500)])
+    g = synth.geometry("grid1k")
+    pts = np.concatenate([synth.points("grid1k", 20000), boundary_points(g, 500)])
     want = oracle.brute(g.vert_off, g.verts, pts)
     rng = np.random.default_rng(5)
     for t in range(3):
@@ -228,13 +228,13 @@ def test_overlapping_blocks_smallest_id(torch_cuda, bm):
 
 def test_save_load_roundtrip(torch_cuda, bm, tmp_path):
     say("save/load")
-    g = synth.geometry(1)
+    g = synth.geometry("grid1k")
     ix = bm.Index.from_geometry(g)
-    p = str(tmp_path / "cfg1.bmi")
+    p = str(tmp_path / "grid1k.bmi")
     ix.save(p)
     ix2 = bm.Index.load(p)
     assert ix2.info()["n_blocks"] == g.n_blocks
-    pts = synth.points(1, 10000)
+    pts = synth.points("grid1k", 10000)
     assert (gpu_map(bm, torch_cuda, ix2, pts) == gpu_map(bm, torch_cuda, ix, pts)).all()
     with open(p, "r+b") as f:
         f.seek(12)
@@ -269,8 +269,8 @@ def test_quantized_points_map_like_the_oracle(torch_cuda, bm):
     reference quantiser's output."""
     from oracle import pyref
     say("quantise + map")
-    g = synth.geometry(1)
-    # a grid of blocks laid over lon/lat: scale config 1 into [2^30, 2^30 + 1e6)
+    g = synth.geometry("grid1k")
+    # a grid of blocks laid over lon/lat: scale grid1k into [2^30, 2^30 + 1e6)
     off, verts = g.vert_off, (g.verts.astype(np.int64) + 2**30).astype(np.int32)
     ix = bm.Index(off, verts, g.n_groups, g.parents)
     rng = np.random.default_rng(10)
@@ -282,15 +282,15 @@ def test_quantized_points_map_like_the_oracle(torch_cuda, bm):
     assert (want >= 0).any() and (want == -1).any()
 
 
-# ------------------------------------------------------------ config 3 ----
+# ------------------------------------------------------------ quadtree8m ----
 
-def test_config3_streamed_billion_points(torch_cuda, bm):
+def test_quadtree8m_streamed_billion_points(torch_cuda, bm):
     """8M-block graded mesh, 1B points in 2^26-point chunks: every output obeys
     the partition property, a full 8M slice equals the hierarchy oracle, and
     sampled points equal brute force."""
     torch = torch_cuda
-    say("config3: generating geometry")
-    g = synth.geometry(3)
+    say("quadtree8m: generating geometry")
+    g = synth.geometry("quadtree8m")
     ix = bm.Index.from_geometry(g)
     H = oracle.Hier.from_geometry(g)
     q = synth.QUADTREE
@@ -299,7 +299,7 @@ def test_config3_streamed_billion_points(torch_cuda, bm):
     out = torch.empty(CH, dtype=torch.int32, device="cuda")
     for k in range((N + CH - 1) // CH):
         n = min(CH, N - k * CH)
-        pts = synth.points(3, n, i0=k * CH)
+        pts = synth.points("quadtree8m", n, i0=k * CH)
         xy = torch.from_numpy(pts).cuda()
         bm.map_points(ix, xy, out[:n])
         got = out[:n].cpu().numpy()
@@ -310,7 +310,7 @@ def test_config3_streamed_billion_points(torch_cuda, bm):
         assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all(), k
         if k == 0:
             assert (got[:8_000_000] == H.map(pts[:8_000_000])).all()
-        say("config3 chunk", k, "ok", n)
+        say("quadtree8m chunk", k, "ok", n)
 
 
 # ------------------------------------------------------- batched form ----
@@ -319,15 +319,15 @@ def _cluster_batches(g, sizes, seed):
     """One Gaussian cluster per batch (the batched workload's recipe)."""
     out = []
     for b, n in enumerate(sizes):
-        m = synth.Mixture(synth.key(4, 2, seed * 100000 + b), 1, g.W, 0.0, 0.001, 0.05, 0.0)
-        out.append(m.sample(synth.key(4, 3, seed * 100000 + b), 0, int(n)))
+        m = synth.Mixture(synth.key("batches10k", 2, seed * 100000 + b), 1, g.W, 0.0, 0.001, 0.05, 0.0)
+        out.append(m.sample(synth.key("batches10k", 3, seed * 100000 + b), 0, int(n)))
     return out
 
 
-def test_batched_equals_plain_per_batch(torch_cuda, bm, cfg2):
+def test_batched_equals_plain_per_batch(torch_cuda, bm, grid221k):
     torch = torch_cuda
-    g, ix, H = cfg2
-    sizes = synth.sizes(synth.key(4, 2, 0), 300, 0, 0, 0, 200_000)
+    g, ix, H = grid221k
+    sizes = synth.sizes(synth.key("batches10k", 2, 0), 300, 0, 0, 0, 200_000)
     sizes[:5] = [0, 1, 63, 64, 65]
     say("batched: %d batches, %d points" % (len(sizes), sizes.sum()))
     pts = _cluster_batches(g, sizes, 1)
@@ -347,14 +347,14 @@ def test_batched_equals_plain_per_batch(torch_cuda, bm, cfg2):
     assert (got[sub] == H.map(allp[sub])).all()
 
 
-def test_batch_plan_graph_replays(torch_cuda, bm, cfg2):
+def test_batch_plan_graph_replays(torch_cuda, bm, grid221k):
     """Captured graph replayed with different tables; eager work and syncs in
     between; every replay equals the plain result."""
     torch = torch_cuda
-    g, ix, H = cfg2
+    g, ix, H = grid221k
     plan = bm.BatchPlan(ix, 64, bm.Tuning(8, 4, 512))
     for rep in range(4):
-        sizes = synth.sizes(synth.key(4, 2, 10 + rep), 10 + 13 * rep, 0, 0, 0, 50_000)
+        sizes = synth.sizes(synth.key("batches10k", 2, 10 + rep), 10 + 13 * rep, 0, 0, 0, 50_000)
         say("plan replay", rep, len(sizes), sizes.sum())
         pts = _cluster_batches(g, sizes, 20 + rep)
         xys = [torch.from_numpy(p).cuda() for p in pts]
@@ -369,11 +369,11 @@ def test_batch_plan_graph_replays(torch_cuda, bm, cfg2):
     plan.close()
 
 
-def test_autotune_never_changes_results(torch_cuda, bm, cfg2, tmp_path, monkeypatch):
+def test_autotune_never_changes_results(torch_cuda, bm, grid221k, tmp_path, monkeypatch):
     torch = torch_cuda
-    g, ix, H = cfg2
+    g, ix, H = grid221k
     monkeypatch.setenv("BM_TUNE_CACHE", str(tmp_path / "tune.txt"))
-    pts = synth.points(2, 2_000_000)
+    pts = synth.points("grid221k", 2_000_000)
     xy = torch.from_numpy(pts).cuda()
     say("autotune")
     t = bm.autotune(ix, xy)
@@ -389,17 +389,17 @@ def test_autotune_never_changes_results(torch_cuda, bm, cfg2, tmp_path, monkeypa
 def _requests(g, sizes, seed):
     out = []
     for r, n in enumerate(sizes):
-        m = synth.Mixture(synth.key(5, 2, seed * 100000 + r), 1, g.W, 0.0, 0.001, 0.02, 0.2)
-        out.append(m.sample(synth.key(5, 3, seed * 100000 + r), 0, int(n)))
+        m = synth.Mixture(synth.key("requests20k", 2, seed * 100000 + r), 1, g.W, 0.0, 0.001, 0.02, 0.2)
+        out.append(m.sample(synth.key("requests20k", 3, seed * 100000 + r), 0, int(n)))
     return out
 
 
-def test_server_results_same_alone_and_in_the_mix(torch_cuda, bm, cfg2):
+def test_server_results_same_alone_and_in_the_mix(torch_cuda, bm, grid221k):
     """Requests submitted together, coalesced into shared device batches (and
     split across batches when large), give exactly the ids each gets alone."""
     torch = torch_cuda
-    g, ix, H = cfg2
-    sizes = list(synth.sizes(synth.key(5, 2, 0), 300, 1, 2000.0, 1.5, 300_000))
+    g, ix, H = grid221k
+    sizes = list(synth.sizes(synth.key("requests20k", 2, 0), 300, 1, 2000.0, 1.5, 300_000))
     sizes[:4] = [0, 1, 64, 250_000]
     reqs = _requests(g, sizes, 1)
     alone = [gpu_map(bm, torch, ix, p) for p in reqs]
@@ -420,8 +420,8 @@ def test_server_results_same_alone_and_in_the_mix(torch_cuda, bm, cfg2):
         assert st["mean_requests_per_batch"] > 1.0  # requests really shared batches
 
 
-def test_server_backpressure_timeout_and_failure(torch_cuda, bm, cfg2):
-    g, ix, H = cfg2
+def test_server_backpressure_timeout_and_failure(torch_cuda, bm, grid221k):
+    g, ix, H = grid221k
     pts = _requests(g, [1000, 1000, 1000], 2)
     outs = [np.empty(1000, np.int32) for _ in pts]
     # a long coalescing window keeps the first pieces queued: the queue fills
@@ -449,9 +449,9 @@ def test_server_backpressure_timeout_and_failure(torch_cuda, bm, cfg2):
     assert e.value.code == bm.BM_EINVAL
 
 
-def test_server_poisson_trace(torch_cuda, bm, cfg2):
-    g, ix, H = cfg2
-    sizes = synth.sizes(synth.key(5, 2, 7), 2000, 1, 10_000.0, 2.0, 2_000_000)
+def test_server_poisson_trace(torch_cuda, bm, grid221k):
+    g, ix, H = grid221k
+    sizes = synth.sizes(synth.key("requests20k", 2, 7), 2000, 1, 10_000.0, 2.0, 2_000_000)
     reqs = _requests(g, sizes, 3)
     outs = [np.full(p.shape[0], -7, np.int32) for p in reqs]
     rng = np.random.default_rng(0)

@@ -56,16 +56,16 @@ def slab_of(ix, nb, py):
 
 
 @pytest.fixture(scope="module")
-def cfg2_index(tmp_path_factory):
+def grid221k_index(tmp_path_factory):
     import paper_2005_03156_amd as bm
-    g = synth.geometry(2)
+    g = synth.geometry("grid221k")
     p = str(tmp_path_factory.mktemp("idx") / "c2.bmi")
     bm.build_index_file(p, g.vert_off, g.verts, g.n_groups, g.parents)
     return g, read_index(p)
 
 
-def test_structure_and_boxes(cfg2_index):
-    g, ix = cfg2_index
+def test_structure_and_boxes(grid221k_index):
+    g, ix = grid221k_index
     B, lb = ix["n_leaves"], ix["leaf_base"]
     assert B == g.n_blocks and lb == sum(g.n_groups) and ix["g0"] == g.n_groups[0]
     assert ix["n_verts"] == g.verts.shape[0]
@@ -97,8 +97,8 @@ def _table_candidates(ix, crec, gbox, px, py):
     return int(ix["slot_mask"][off + sx]) & int(ix["slot_mask"][off + S + sy])
 
 
-def test_slot_tables_are_supersets(cfg2_index):
-    g, ix = cfg2_index
+def test_slot_tables_are_supersets(grid221k_index):
+    g, ix = grid221k_index
     rng = np.random.default_rng(2)
     groups = [(ix["root_child"], ix["root_box"])]
     tabbed = np.flatnonzero(ix["child"][:, 2] >= 0)
@@ -118,11 +118,11 @@ def test_slot_tables_are_supersets(cfg2_index):
             assert cand >> (c1 - c0) == 0
 
 
-def test_y_slabs_list_every_straddling_edge(cfg2_index):
+def test_y_slabs_list_every_straddling_edge(grid221k_index):
     """For any height in a leaf's y-extent, its slab lists (as vertex pairs)
     every edge of the caller's ring that straddles that height, and only
     edges of that ring."""
-    g, ix = cfg2_index
+    g, ix = grid221k_index
     rng = np.random.default_rng(3)
     for nb in rng.choice(ix["n_leaves"], 300, replace=False):
         b = int(ix["leaf"]["leaf_id"][nb])
@@ -140,11 +140,11 @@ def test_y_slabs_list_every_straddling_edge(cfg2_index):
             assert len(listed) <= len(ring)
 
 
-def test_y_slab_parity_equals_oracle(cfg2_index):
+def test_y_slab_parity_equals_oracle(grid221k_index):
     """Crossing parity over the listed slab edges only (intersections computed
     with exact rationals) equals the oracle's parity over the full ring."""
     from fractions import Fraction
-    g, ix = cfg2_index
+    g, ix = grid221k_index
     rng = np.random.default_rng(4)
     for nb in rng.choice(ix["n_leaves"], 60, replace=False):
         b = int(ix["leaf"]["leaf_id"][nb])

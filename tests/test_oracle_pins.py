@@ -185,8 +185,8 @@ def test_metamorphic_invariances():
 
 
 def test_block_permutation():
-    g = synth.geometry(1)
-    pts = synth.points(1, 3000)
+    g = synth.geometry("grid1k")
+    pts = synth.points("grid1k", 3000)
     base = oracle.brute(g.vert_off, g.verts, pts)
     rng = np.random.default_rng(9)
     perm = rng.permutation(g.n_blocks)  # new block q holds old block perm[q]
@@ -220,19 +220,19 @@ def test_unjittered_grid_closed_form():
     assert (oracle.Hier(off, verts, ng, par).map(pts) == want).all()
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_partition_invariant(cfg):
+@pytest.mark.parametrize("workload", ["grid1k", "grid221k"])
+def test_partition_invariant(workload):
     """Watertight partition of [0, W)^2: a point inside the square lies in exactly
     one block, a point outside in none."""
-    g = synth.geometry(cfg)
-    pts = synth.points(cfg, 100_000 if cfg == 1 else 2000)
+    g = synth.geometry(workload)
+    pts = synth.points(workload, 100_000 if workload == "grid1k" else 2000)
     # extra points on the hull, its corners and grid vertices
     W = g.W
     edge = np.array([[0, 5], [5, 0], [W - 1, 7], [7, W - 1], [W, 3], [3, W], [0, 0], [W - 1, W - 1],
                      [W, W], [-1, 0], [0, -1]], np.int32)
     v = g.verts[np.random.default_rng(2).choice(g.verts.shape[0], 400, replace=False)]
     pts = np.concatenate([pts, edge, v, v + 1, v - 1]).astype(np.int32)
-    out, hits = oracle.brute(g.vert_off, g.verts, pts, box_reject=(cfg != 1), count_hits=True)
+    out, hits = oracle.brute(g.vert_off, g.verts, pts, box_reject=(workload != "grid1k"), count_hits=True)
     x, y = pts[:, 0].astype(np.int64), pts[:, 1].astype(np.int64)
     inside = (x >= 0) & (x < W) & (y >= 0) & (y < W)
     assert (hits[inside] == 1).all()
@@ -240,18 +240,18 @@ def test_partition_invariant(cfg):
     assert ((out >= 0) == inside).all()
 
 
-def test_hier_equals_brute_config1():
-    g = synth.geometry(1)
-    pts = synth.points(1)
+def test_hier_equals_brute_grid1k():
+    g = synth.geometry("grid1k")
+    pts = synth.points("grid1k")
     want = oracle.brute(g.vert_off, g.verts, pts)
     got, cnt = oracle.Hier.from_geometry(g).map(pts, with_counts=True)
     assert (got == want).all()
     assert cnt["hits"] == int((want >= 0).sum())
 
 
-def test_hier_equals_brute_config2_sample():
-    g = synth.geometry(2)
-    pts = synth.points(2, 200_000)
+def test_hier_equals_brute_grid221k_sample():
+    g = synth.geometry("grid221k")
+    pts = synth.points("grid221k", 200_000)
     got = oracle.Hier.from_geometry(g).map(pts)
     sub = np.random.default_rng(4).choice(pts.shape[0], 1500, replace=False)
     want = oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)
@@ -262,8 +262,8 @@ def test_hier_any_grouping_is_exact():
     """Group boxes are unions of their children's boxes, so the hierarchy never
     loses a containing block, whatever the grouping: random regroupings and
     extra levels give the definition's answer."""
-    g = synth.geometry(1)
-    pts = synth.points(1, 20000)
+    g = synth.geometry("grid1k")
+    pts = synth.points("grid1k", 20000)
     want = oracle.brute(g.vert_off, g.verts, pts)
     rng = np.random.default_rng(6)
     for t in range(4):

@@ -22,7 +22,7 @@ def _vertex_probes(g, k, seed):
 
 def test_quadtree_mesh_is_watertight_and_hierarchy_exact():
     q, g = _small_quadtree()
-    pts = np.concatenate([synth.quadtree_mixture(q).sample(synth.key(3, 1, 1), 0, 20000),
+    pts = np.concatenate([synth.quadtree_mixture(q).sample(synth.key("quadtree8m", 1, 1), 0, 20000),
                           _vertex_probes(g, 3000, 0)]).astype(np.int32)
     out, hits = oracle.brute(g.vert_off, g.verts, pts, box_reject=True, count_hits=True)
     x, y = pts[:, 0].astype(np.int64), pts[:, 1].astype(np.int64)
@@ -43,8 +43,8 @@ def test_quadtree_t_junctions_present():
     assert (np.abs(np.diff(d.astype(int), axis=1)) == 1).any()
 
 
-def test_config3_shape():
-    g = synth.geometry(3)
+def test_quadtree8m_shape():
+    g = synth.geometry("quadtree8m")
     nv = np.diff(g.vert_off)
     assert abs(g.n_blocks - 8_000_000) < 80_000
     assert nv.min() >= 4 and nv.max() <= 2000
@@ -57,11 +57,11 @@ def test_config3_shape():
         assert np.bincount(p).max() <= 64  # fan-out <= 64 at every level
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_grid_config_shape(cfg):
-    g = synth.geometry(cfg)
+@pytest.mark.parametrize("workload", ["grid1k", "grid221k"])
+def test_grid_shape(workload):
+    g = synth.geometry(workload)
     nv = np.diff(g.vert_off)
-    if cfg == 1:
+    if workload == "grid1k":
         assert g.n_blocks == 1024 and nv.min() >= 16 and nv.max() <= 28
     else:
         assert g.n_blocks == 220_900 and 23 <= nv.mean() <= 25 and nv.max() <= 4 + 4 * 40
@@ -70,8 +70,8 @@ def test_grid_config_shape(cfg):
 
 def test_points_are_counter_based():
     """Any slice of a point stream can be regenerated on its own."""
-    a = synth.points(2, 10_000)
-    b = synth.points(2, 4_000, i0=6_000)
+    a = synth.points("grid221k", 10_000)
+    b = synth.points("grid221k", 4_000, i0=6_000)
     assert (a[6_000:] == b).all()
-    c = synth.points(3, 1000, i0=(1 << 26) * 3)
+    c = synth.points("quadtree8m", 1000, i0=(1 << 26) * 3)
     assert c.shape == (1000, 2)
