@@ -396,7 +396,9 @@ int map_points_cover(const bm_cover* cover, const int32_t* xy, int64_t n, int32_
  * written by map_points), adds to counts[b] (device, n_blocks + 1 uint64) the
  * number of ids equal to b, for b in [0, n_blocks), and to counts[n_blocks]
  * the number of the others (-1: no block). Counts accumulate: clear them first
- * for a fresh count. Asynchronous on `stream`.
+ * for a fresh count. Asynchronous on `stream`. Calls of 2^20 ids or more use
+ * stream-ordered scratch (hipMallocAsync) of about 4 bytes per id plus
+ * 32 KiB per 8192 blocks per slice.
  * Errors: BM_EINVAL (null buffer, n < 0, n_blocks outside [0, 2^31 - 2]), BM_EHIP. */
 int bm_count_per_block(const int32_t* ids, int64_t n, int64_t n_blocks, uint64_t* counts, hipStream_t stream);
 

@@ -693,6 +693,91 @@ __global__ __launch_bounds__(256) void count_kernel(const int* __restrict__ ids,
   }
 }
 
+// Bucketed count for large calls: ids are counting-sorted by bucket id >> 13
+// (at most kBins buckets of 8192 ids; the binning passes above with a
+// different key), then each slice of a bucket is counted in an LDS histogram
+// into its own row of partial counts, and the rows are summed. No two
+// threads then add to one global counter.
+constexpr int kCntShift = 13;
+constexpr int kCntIds = 1 << kCntShift;
+
+__global__ __launch_bounds__(1024) void cnt_bucket_count_kernel(const int* __restrict__ ids, const long long n,
+                                                                const int nb, const long long per,
+                                                                unsigned* __restrict__ tot,
+                                                                unsigned long long* __restrict__ counts) {
+  __shared__ unsigned h[kBins];
+  __shared__ unsigned other;
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
+  if (threadIdx.x == 0) other = 0;
+  __syncthreads();
+  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int id = ids[i];
+    if (id >= 0 && id < nb)
+      atomicAdd(&h[id >> kCntShift], 1u);
+    else
+      atomicAdd(&other, 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    if (h[i]) atomicAdd(&tot[i], h[i]);
+  if (threadIdx.x == 0 && other) atomicAdd(&counts[nb], (unsigned long long)other);
+}
+
+__global__ __launch_bounds__(1024) void cnt_bucket_scatter_kernel(const int* __restrict__ ids, const long long n,
+                                                                  const int nb, const long long per,
+                                                                  unsigned* __restrict__ cursor,
+                                                                  int* __restrict__ sorted) {
+  __shared__ unsigned cur[kBins];
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) cur[i] = 0;
+  __syncthreads();
+  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int id = ids[i];
+    if (id >= 0 && id < nb) atomicAdd(&cur[id >> kCntShift], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    if (cur[i]) cur[i] = atomicAdd(&cursor[i], cur[i]);
+  __syncthreads();
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int id = ids[i];
+    if (id >= 0 && id < nb) sorted[atomicAdd(&cur[id >> kCntShift], 1u)] = id;
+  }
+}
+
+// Block (bucket b = blockIdx.x, slice s = blockIdx.y) counts its slice of the
+// bucket's segment [end[b-1], end[b]) of `sorted` into part[s][b * 8192 + k].
+__global__ __launch_bounds__(1024) void cnt_slice_kernel(const int* __restrict__ sorted,
+                                                         const unsigned* __restrict__ end, const int nb,
+                                                         unsigned* __restrict__ part, const long long part_stride) {
+  __shared__ unsigned h[kCntIds];
+  for (int i = threadIdx.x; i < kCntIds; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const int b = blockIdx.x, sl = blockIdx.y, ns = gridDim.y;
+  const long long s0 = b ? end[b - 1] : 0, s1 = end[b];
+  const long long len = s1 - s0, per = (len + ns - 1) / ns;
+  const long long lo = s0 + (long long)sl * per, hi = min(s1, lo + per);
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[sorted[i] & (kCntIds - 1)], 1u);
+  __syncthreads();
+  const long long base = (long long)b * kCntIds;
+  unsigned* row = part + (long long)sl * part_stride + base;
+  for (int i = threadIdx.x; i < kCntIds; i += blockDim.x)
+    if (base + i < nb) row[i] = h[i];
+}
+
+// counts[id] += sum over slices of part[s][id], for id < nb.
+__global__ __launch_bounds__(256) void cnt_reduce_kernel(const unsigned* __restrict__ part, const int ns,
+                                                         const long long part_stride, const int nb,
+                                                         unsigned long long* __restrict__ counts) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < nb; id += stride) {
+    unsigned long long t = 0;
+    for (int sl = 0; sl < ns; ++sl) t += part[(long long)sl * part_stride + id];
+    counts[id] += t;
+  }
+}
+
 // Quantiser: q = rint(v * 2^22) + 2^30 per axis; invalid input -> (-1, -1).
 // The product by a power of two is exact, so rint is the only rounding.
 __global__ __launch_bounds__(256) void quantize_kernel(const double2* __restrict__ ll,
@@ -851,6 +936,36 @@ hipError_t launch_cover(const KIndex& ix, const KCover& cv, const int32_t* xy, i
 
 hipError_t launch_count(const int32_t* ids, int64_t n, int32_t nb, unsigned long long* counts, int num_cu,
                         hipStream_t stream) {
+  const long long nbk = ((long long)nb + kCntIds - 1) / kCntIds;
+  if (n >= kPresortMin && nbk >= 1 && nbk <= kBins) {
+    // bucketed: no contended global atomics
+    const int ns = (int)std::max<long long>(1, std::min<long long>(64, (4LL * num_cu + nbk - 1) / nbk));
+    const long long part_stride = nbk * kCntIds;
+    const size_t bytes = sizeof(unsigned) * (2 * (size_t)kBins + (size_t)ns * part_stride) + sizeof(int) * (size_t)n;
+    void* scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, bytes, stream);
+    if (e != hipSuccess) return e;
+    unsigned* tot = static_cast<unsigned*>(scratch);
+    unsigned* cursor = tot + kBins;
+    unsigned* part = cursor + kBins;
+    int* sorted = reinterpret_cast<int*>(part + (size_t)ns * part_stride);
+    const int nblk = kBinBlocks;
+    const long long per = (n + nblk - 1) / nblk;
+    hipLaunchKernelGGL(bin_zero_kernel, dim3(1), dim3(1024), 0, stream, tot);
+    hipLaunchKernelGGL(cnt_bucket_count_kernel, dim3(nblk), dim3(1024), 0, stream, reinterpret_cast<const int*>(ids),
+                       (long long)n, nb, per, tot, counts);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, stream, tot, cursor);
+    hipLaunchKernelGGL(cnt_bucket_scatter_kernel, dim3(nblk), dim3(1024), 0, stream,
+                       reinterpret_cast<const int*>(ids), (long long)n, nb, per, cursor, sorted);
+    hipLaunchKernelGGL(cnt_slice_kernel, dim3((unsigned)nbk, (unsigned)ns), dim3(1024), 0, stream, sorted, cursor, nb,
+                       part, part_stride);
+    const long long rb = std::min<long long>(((long long)nb + 255) / 256, (long long)num_cu * 8);
+    hipLaunchKernelGGL(cnt_reduce_kernel, dim3((unsigned)std::max<long long>(1, rb)), dim3(256), 0, stream, part, ns,
+                       part_stride, nb, counts);
+    e = hipGetLastError();
+    const hipError_t e2 = hipFreeAsync(scratch, stream);
+    return e != hipSuccess ? e : e2;
+  }
   long long blocks = (n + 255) / 256;
   const long long cap = (long long)num_cu * 16;
   if (blocks > cap) blocks = cap;

@@ -201,3 +201,19 @@ def test_count_per_block(torch_cuda, bm):
     assert np.array_equal(c.cpu().numpy(), 2 * bm.count_per_block(ids, g.n_blocks).cpu().numpy())
     names, cnt = bm.join_per_block(c, np.array(["b%d" % b for b in range(g.n_blocks)]))
     assert cnt.sum() == 2 * int((ids.cpu().numpy() >= 0).sum()) and len(names) == len(cnt)
+
+
+@pytest.mark.parametrize("nb", [1024, 220_900, 3_000_001])
+def test_count_per_block_bucketed(torch_cuda, bm, nb):
+    """Large calls take the bucketed route (counting sort by id >> 13, LDS
+    histograms per slice, summed rows): the same counts as bincount."""
+    torch = torch_cuda
+    rng = np.random.default_rng(nb)
+    a = rng.integers(-3, nb + 3, size=3_000_000).astype(np.int32)
+    a[:1000] = nb - 1  # a crowded block
+    for order in ("random", "sorted"):
+        say("bucketed count", nb, order)
+        t = torch.from_numpy(np.sort(a) if order == "sorted" else a).cuda()
+        got = bm.count_per_block(t, nb).cpu().numpy()
+        b = np.where((a >= 0) & (a < nb), a, nb).astype(np.int64)
+        assert np.array_equal(got, np.bincount(b, minlength=nb + 1)), order
