@@ -59,8 +59,8 @@ typedef struct bm_index bm_index;
  * state -> county -> block, here any number of group levels).
  *
  *   n_blocks      number of blocks. Block b keeps the index b in every result.
- *                 Blocks plus the groups of all levels: at most 2^25
- *                 (33,554,432) nodes.
+ *                 Blocks plus the groups of all levels: at most 2^26
+ *                 (67,108,864) nodes.
  *   vert_off      [n_blocks + 1] int64, vert_off[0] = 0, non-decreasing: ring b
  *                 is verts_xy[2*vert_off[b] .. 2*vert_off[b+1]).
  *   verts_xy      interleaved (x, y) int32 vertices, each coordinate in
@@ -92,7 +92,7 @@ typedef struct {
  * by the caller until bm_index_destroy. Synchronous.
  * Errors: BM_EINVAL (null pointer, bad sizes or offsets, ring with fewer than
  * 3 vertices, parent out of range), BM_ERANGE (coordinate outside
- * [0, 2^31 - 1], more than 2^25 nodes, or slab edge lists of 2^31 or more
+ * [0, 2^31 - 1], more than 2^26 nodes, or slab edge lists of 2^31 or more
  * entries), BM_ENOMEM, BM_EHIP. */
 int bm_index_create(const bm_index_desc* desc, bm_index** out);
 

@@ -46,7 +46,7 @@ static_assert(offsetof(LeafRec, ent) == 16 && offsetof(LeafRec, leaf_id) == 24 &
 // of `ent` carries kEntPad zero entries at its end, so a crossing-test chunk
 // may load past its list.
 #ifndef BM_TILE_PTS
-#define BM_TILE_PTS 2
+#define BM_TILE_PTS 1
 #endif
 constexpr int kTilePts = BM_TILE_PTS;
 static_assert(kTilePts == 1 || kTilePts == 2 || kTilePts == 4, "1, 2 or 4 points per lane");

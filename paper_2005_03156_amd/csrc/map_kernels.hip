@@ -556,7 +556,9 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map
 // order does not change any output.
 constexpr int kBinBits = 6;  // per axis
 constexpr int kBins = 1 << (2 * kBinBits);
-constexpr int kBinBlocks = 256;  // blocks of the count and scatter passes
+constexpr int kBinThreads = 1024;  // threads per block of the count and scatter passes
+constexpr int kBinPer = 16;        // points per thread: all loaded before any LDS atomic
+constexpr long long kBinBlockPts = (long long)kBinThreads * kBinPer;
 
 __device__ __forceinline__ unsigned spread6(unsigned v) {
   v &= 63u;
@@ -574,46 +576,109 @@ __device__ __forceinline__ unsigned bin_of(const int2 p, const int4 rb, const in
   return spread6(cx) | (spread6(cy) << 1);
 }
 
-// Each block counts the bins of its range of the chunk in LDS and adds the
-// counts to the chunk's per-bin totals.
-__global__ __launch_bounds__(1024) void bin_count_kernel(const int2* __restrict__ xy, const long long n,
-                                                         const long long per, const int4 rb, const int shx,
-                                                         const int shy, unsigned* __restrict__ tot) {
+// Exclusive prefix sum over a block of kThreads threads; `wsum` holds one
+// entry per wave. Every thread of the block must call it.
+template <int kThreads>
+__device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* wsum) {
+  constexpr int kW = kThreads / kWave;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  unsigned inc = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    unsigned s = lane < kW ? wsum[lane] : 0u;
+#pragma unroll
+    for (int o = 1; o < kW; o <<= 1) {
+      const unsigned t = __shfl_up(s, o);
+      if (lane >= o) s += t;
+    }
+    if (lane < kW) wsum[lane] = s;  // inclusive prefix over waves
+  }
+  __syncthreads();
+  return (w ? wsum[w - 1] : 0u) + inc - v;
+}
+
+// Both passes give block b the kBinBlockPts points starting at b * kBinBlockPts,
+// thread t the points t, t + kBinThreads, ... of that range, and load all of a
+// thread's points before the first LDS atomic, so the loads of a block are in
+// flight together rather than one per loop trip.
+__device__ __forceinline__ void bin_load(const int2* __restrict__ xy, const long long n, const int4 rb,
+                                         const int shx, const int shy, int2 (&p)[kBinPer],
+                                         unsigned (&b)[kBinPer]) {
+  const long long lo = (long long)blockIdx.x * kBinBlockPts + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k) {
+    const long long i = lo + (long long)k * kBinThreads;
+    p[k] = i < n ? xy[i] : make_int2(0, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k)
+    b[k] = lo + (long long)k * kBinThreads < n ? bin_of(p[k], rb, shx, shy) : (unsigned)kBins;
+}
+
+// Each block counts the bins of its range in LDS and adds the counts to the
+// chunk's per-bin totals.
+__global__ __launch_bounds__(kBinThreads) void bin_count_kernel(const int2* __restrict__ xy, const long long n,
+                                                                const int4 rb, const int shx, const int shy,
+                                                                unsigned* __restrict__ tot) {
   __shared__ unsigned h[kBins];
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
+  int2 p[kBinPer];
+  unsigned b[kBinPer];
+  bin_load(xy, n, rb, shx, shy, p, b);
+  for (int i = threadIdx.x; i < kBins; i += kBinThreads) h[i] = 0;
   __syncthreads();
-  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[bin_of(xy[i], rb, shx, shy)], 1u);
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k)
+    if (b[k] < (unsigned)kBins) atomicAdd(&h[b[k]], 1u);
   __syncthreads();
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+  for (int i = threadIdx.x; i < kBins; i += kBinThreads)
     if (h[i]) atomicAdd(&tot[i], h[i]);
 }
 
+// The refinement pass cuts every bin into pieces of kRefPts points.
+constexpr int kSubBits = 4;  // per axis: 16 x 16 sub-cells per bin
+constexpr int kSubs = 1 << (2 * kSubBits);
+constexpr int kRefThreads = 256;
+constexpr int kRefPer = 8;
+constexpr int kRefPts = kRefThreads * kRefPer;
+
 // cursor[bin] = first sorted position of the bin (exclusive scan of tot);
-// tot is cleared for the next chunk. One block.
-__global__ __launch_bounds__(1024) void bin_scan_kernel(unsigned* __restrict__ tot, unsigned* __restrict__ cursor) {
-  constexpr int kPer = kBins / 1024;
-  __shared__ unsigned part[1024];
-  unsigned v[kPer], mine = 0;
+// tot is cleared for the next chunk. With `pstart`, also the bins' first
+// piece numbers (exclusive scan of ceil(tot / kRefPts)) and, in
+// pstart[kBins], the number of pieces. One block of kBinThreads.
+__global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(unsigned* __restrict__ tot,
+                                                               unsigned* __restrict__ cursor,
+                                                               unsigned* __restrict__ pstart) {
+  constexpr int kPer = kBins / kBinThreads;
+  __shared__ unsigned wsum[kBinThreads / kWave];
+  unsigned v[kPer], mine = 0, pcs = 0;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     v[k] = tot[threadIdx.x * kPer + k];
     mine += v[k];
+    pcs += (v[k] + kRefPts - 1) / kRefPts;
   }
-  part[threadIdx.x] = mine;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const unsigned t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += t;
-    __syncthreads();
-  }
-  unsigned run = part[threadIdx.x] - mine;
+  unsigned run = block_exclusive_scan<kBinThreads>(mine, wsum);
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     cursor[threadIdx.x * kPer + k] = run;
     tot[threadIdx.x * kPer + k] = 0;
     run += v[k];
+  }
+  if (pstart) {
+    __syncthreads();  // wsum is reused
+    unsigned pr = block_exclusive_scan<kBinThreads>(pcs, wsum);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      pstart[threadIdx.x * kPer + k] = pr;
+      pr += (v[k] + kRefPts - 1) / kRefPts;
+    }
+    if (threadIdx.x == kBinThreads - 1) pstart[kBins] = pr;
   }
 }
 
@@ -621,28 +686,144 @@ __global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ t
   for (int i = threadIdx.x; i < kBins; i += blockDim.x) tot[i] = 0;
 }
 
-// Each block recounts its range, reserves a run of every bin it uses from the
-// bin cursors, and scatters its points into those runs: sorted[pos] = point,
-// perm[pos] = its index in the chunk. (The order inside a bin varies from run
-// to run; no output depends on it.)
-__global__ __launch_bounds__(1024) void bin_scatter_kernel(const int2* __restrict__ xy, const long long n,
-                                                           const long long per, const int4 rb, const int shx,
-                                                           const int shy, unsigned* __restrict__ cursor,
-                                                           int2* __restrict__ sorted, int* __restrict__ perm) {
-  __shared__ unsigned cur[kBins];
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x) cur[i] = 0;
+// The scatter pass gives each block kScatPts points (kScatPer per thread).
+// A block ranks its points by bin in LDS, reserves one run of every bin it
+// uses from the bin cursors, lays the points out in LDS in bin order, and
+// then stores them with consecutive threads on consecutive positions of the
+// runs, so a wave's stores touch a few cache lines rather than one per lane:
+// sorted[pos] = point, perm[pos] = its index in the chunk. (The order inside
+// a bin varies from run to run; no output depends on it.)
+constexpr int kScatPer = 8;
+constexpr long long kScatPts = (long long)kBinThreads * kScatPer;
+
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __restrict__ xy, const long long n,
+                                                                  const int4 rb, const int shx, const int shy,
+                                                                  unsigned* __restrict__ cursor,
+                                                                  int2* __restrict__ sorted, int* __restrict__ perm) {
+  __shared__ int2 sx[kScatPts];
+  __shared__ unsigned short si[kScatPts];
+  __shared__ unsigned h[kBins];  // counts, then first local position of each bin
+  __shared__ unsigned d[kBins];  // first global position minus first local position
+  __shared__ unsigned wsum[kBinThreads / kWave];
+  const long long lo = (long long)blockIdx.x * kScatPts;
+  int2 p[kScatPer];
+  unsigned b[kScatPer], r[kScatPer];
+#pragma unroll
+  for (int k = 0; k < kScatPer; ++k) {
+    const long long i = lo + threadIdx.x + (long long)k * kBinThreads;
+    p[k] = i < n ? xy[i] : make_int2(0, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < kScatPer; ++k)
+    b[k] = lo + threadIdx.x + (long long)k * kBinThreads < n ? bin_of(p[k], rb, shx, shy) : (unsigned)kBins;
+  for (int i = threadIdx.x; i < kBins; i += kBinThreads) h[i] = 0;
   __syncthreads();
-  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cur[bin_of(xy[i], rb, shx, shy)], 1u);
+#pragma unroll
+  for (int k = 0; k < kScatPer; ++k) r[k] = b[k] < (unsigned)kBins ? atomicAdd(&h[b[k]], 1u) : 0u;
   __syncthreads();
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
-    if (cur[i]) cur[i] = atomicAdd(&cursor[i], cur[i]);
+  // local starts (exclusive scan of the counts) and the global runs
+  constexpr int kQ = kBins / kBinThreads;
+  unsigned v[kQ], mine = 0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    v[q] = h[threadIdx.x * kQ + q];
+    mine += v[q];
+  }
+  unsigned run = block_exclusive_scan<kBinThreads>(mine, wsum);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int bin = threadIdx.x * kQ + q;
+    if (v[q]) d[bin] = atomicAdd(&cursor[bin], v[q]) - run;
+    h[bin] = run;
+    run += v[q];
+  }
   __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const int2 p = xy[i];
-    const unsigned pos = atomicAdd(&cur[bin_of(p, rb, shx, shy)], 1u);
-    sorted[pos] = p;
-    perm[pos] = (int)i;
+#pragma unroll
+  for (int k = 0; k < kScatPer; ++k)
+    if (b[k] < (unsigned)kBins) {
+      const unsigned j = h[b[k]] + r[k];
+      sx[j] = p[k];
+      si[j] = (unsigned short)(threadIdx.x + k * kBinThreads);
+    }
+  __syncthreads();
+  const int cnt = (int)min((long long)kScatPts, n - lo);
+  for (int j = threadIdx.x; j < cnt; j += kBinThreads) {
+    const int2 q = sx[j];
+    const unsigned pos = d[bin_of(q, rb, shx, shy)] + (unsigned)j;
+    sorted[pos] = q;
+    perm[pos] = (int)(lo + si[j]);
+  }
+}
+
+// Refinement: after the scatter, cursor[bin] is the end of the bin. Block i
+// takes piece i (the bin found by a binary search of pstart) and sorts its
+// points and permutation entries in place by a 16 x 16 Morton sub-cell of the
+// bin's cell, through LDS. Bin and sub-cell together order the chunk along
+// a Z-curve on a 1024 x 1024 grid, so the mapping kernel's tiles of points
+// are spatially tighter. Blocks beyond the last piece exit at once.
+__device__ __forceinline__ unsigned sub_of(const int2 p, const int4 rb, const int shx, const int shy) {
+  const long long dx = (long long)p.x - rb.x, dy = (long long)p.y - rb.z;
+  const long long top = (1ll << (kBinBits + kSubBits)) - 1;
+  const unsigned cx = (unsigned)min(top, max(0ll, dx >> (shx - kSubBits))) & ((1u << kSubBits) - 1);
+  const unsigned cy = (unsigned)min(top, max(0ll, dy >> (shy - kSubBits))) & ((1u << kSubBits) - 1);
+  return spread6(cx) | (spread6(cy) << 1);
+}
+
+__global__ __launch_bounds__(kRefThreads) void bin_refine_kernel(int2* __restrict__ sorted, int* __restrict__ perm,
+                                                                 const unsigned* __restrict__ cursor,
+                                                                 const unsigned* __restrict__ pstart, const int4 rb,
+                                                                 const int shx, const int shy) {
+  __shared__ int2 sx[kRefPts];
+  __shared__ int sp[kRefPts];
+  __shared__ unsigned h[kSubs];
+  __shared__ unsigned wsum[kRefThreads / kWave];
+  __shared__ int the_bin;
+  static_assert(kSubs == kRefThreads, "one sub-cell count per thread");
+  const unsigned piece = blockIdx.x;
+  if (piece >= pstart[kBins]) return;
+  if (threadIdx.x == 0) {  // the last bin whose first piece is <= piece
+    int lo = 0, hi = kBins - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pstart[mid] <= piece) lo = mid; else hi = mid - 1;
+    }
+    the_bin = lo;
+  }
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int b = the_bin;
+  const unsigned start = b ? cursor[b - 1] : 0u, end = cursor[b];
+  const unsigned base = start + (piece - pstart[b]) * (unsigned)kRefPts;
+  const int cnt = (int)min((unsigned)kRefPts, end - base);
+  int2 p[kRefPer];
+  int q[kRefPer];
+  unsigned key[kRefPer], r[kRefPer];
+#pragma unroll
+  for (int k = 0; k < kRefPer; ++k) {
+    const int j = threadIdx.x + k * kRefThreads;
+    p[k] = j < cnt ? sorted[base + j] : make_int2(0, 0);
+    q[k] = j < cnt ? perm[base + j] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kRefPer; ++k) {
+    key[k] = threadIdx.x + k * kRefThreads < cnt ? sub_of(p[k], rb, shx, shy) : (unsigned)kSubs;
+    r[k] = key[k] < (unsigned)kSubs ? atomicAdd(&h[key[k]], 1u) : 0u;
+  }
+  __syncthreads();
+  const unsigned first = block_exclusive_scan<kRefThreads>(h[threadIdx.x], wsum);
+  h[threadIdx.x] = first;  // each thread rewrites only its own sub-cell
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRefPer; ++k)
+    if (key[k] < (unsigned)kSubs) {
+      const unsigned j = h[key[k]] + r[k];
+      sx[j] = p[k];
+      sp[j] = q[k];
+    }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += kRefThreads) {
+    sorted[base + j] = sx[j];
+    perm[base + j] = sp[j];
   }
 }
 
@@ -701,49 +882,68 @@ __global__ __launch_bounds__(256) void count_kernel(const int* __restrict__ ids,
 constexpr int kCntShift = 13;
 constexpr int kCntIds = 1 << kCntShift;
 
-__global__ __launch_bounds__(1024) void cnt_bucket_count_kernel(const int* __restrict__ ids, const long long n,
-                                                                const int nb, const long long per,
-                                                                unsigned* __restrict__ tot,
-                                                                unsigned long long* __restrict__ counts) {
+// Block b takes ids b * kBinBlockPts + t + k * kBinThreads; a thread loads
+// its kBinPer ids before its first LDS atomic. Ids outside [0, nb) get
+// bucket kBins (none).
+__device__ __forceinline__ void cnt_load(const int* __restrict__ ids, const long long n, const int nb,
+                                         int (&id)[kBinPer]) {
+  const long long lo = (long long)blockIdx.x * kBinBlockPts + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k) {
+    const long long i = lo + (long long)k * kBinThreads;
+    id[k] = i < n ? ids[i] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k)
+    if (id[k] >= nb) id[k] = -1;
+}
+
+__global__ __launch_bounds__(kBinThreads) void cnt_bucket_count_kernel(const int* __restrict__ ids,
+                                                                       const long long n, const int nb,
+                                                                       unsigned* __restrict__ tot,
+                                                                       unsigned long long* __restrict__ counts) {
   __shared__ unsigned h[kBins];
   __shared__ unsigned other;
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
+  int id[kBinPer];
+  cnt_load(ids, n, nb, id);
+  for (int i = threadIdx.x; i < kBins; i += kBinThreads) h[i] = 0;
   if (threadIdx.x == 0) other = 0;
   __syncthreads();
-  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const int id = ids[i];
-    if (id >= 0 && id < nb)
-      atomicAdd(&h[id >> kCntShift], 1u);
-    else
-      atomicAdd(&other, 1u);
+  const long long lo = (long long)blockIdx.x * kBinBlockPts + threadIdx.x;
+  unsigned mine = 0;  // this thread's ids in range of the call but not of [0, nb)
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k) {
+    if (id[k] >= 0)
+      atomicAdd(&h[id[k] >> kCntShift], 1u);
+    else if (lo + (long long)k * kBinThreads < n)
+      ++mine;
   }
+  if (mine) atomicAdd(&other, mine);
   __syncthreads();
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+  for (int i = threadIdx.x; i < kBins; i += kBinThreads)
     if (h[i]) atomicAdd(&tot[i], h[i]);
   if (threadIdx.x == 0 && other) atomicAdd(&counts[nb], (unsigned long long)other);
 }
 
-__global__ __launch_bounds__(1024) void cnt_bucket_scatter_kernel(const int* __restrict__ ids, const long long n,
-                                                                  const int nb, const long long per,
-                                                                  unsigned* __restrict__ cursor,
-                                                                  int* __restrict__ sorted) {
+__global__ __launch_bounds__(kBinThreads) void cnt_bucket_scatter_kernel(const int* __restrict__ ids,
+                                                                         const long long n, const int nb,
+                                                                         unsigned* __restrict__ cursor,
+                                                                         int* __restrict__ sorted) {
   __shared__ unsigned cur[kBins];
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x) cur[i] = 0;
+  int id[kBinPer];
+  cnt_load(ids, n, nb, id);
+  for (int i = threadIdx.x; i < kBins; i += kBinThreads) cur[i] = 0;
   __syncthreads();
-  const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const int id = ids[i];
-    if (id >= 0 && id < nb) atomicAdd(&cur[id >> kCntShift], 1u);
-  }
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k)
+    if (id[k] >= 0) atomicAdd(&cur[id[k] >> kCntShift], 1u);
   __syncthreads();
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+  for (int i = threadIdx.x; i < kBins; i += kBinThreads)
     if (cur[i]) cur[i] = atomicAdd(&cursor[i], cur[i]);
   __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const int id = ids[i];
-    if (id >= 0 && id < nb) sorted[atomicAdd(&cur[id >> kCntShift], 1u)] = id;
-  }
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k)
+    if (id[k] >= 0) sorted[atomicAdd(&cur[id[k] >> kCntShift], 1u)] = id[k];
 }
 
 // Block (bucket b = blockIdx.x, slice s = blockIdx.y) counts its slice of the
@@ -859,29 +1059,34 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
   }
   // spatially sorted, chunk by chunk, through stream-ordered scratch
   const long long chunk = std::min<long long>(n, kPresortChunk);
-  const int nblk = kBinBlocks;
-  const size_t hist_bytes = sizeof(unsigned) * 2 * (size_t)kBins;
+  const size_t hist_bytes = sizeof(unsigned) * (3 * (size_t)kBins + 64);
   const size_t bytes = hist_bytes + (size_t)chunk * (sizeof(int2) + sizeof(int)) + 256;
   void* scratch = nullptr;
   hipError_t e = hipMallocAsync(&scratch, bytes, stream);
   if (e != hipSuccess) return e;
   unsigned* tot = static_cast<unsigned*>(scratch);
   unsigned* cursor = tot + kBins;
+  unsigned* pstart = cursor + kBins;  // kBins + 1 entries
   int2* sorted = reinterpret_cast<int2*>(static_cast<char*>(scratch) + hist_bytes);
   int* perm = reinterpret_cast<int*>(sorted + chunk);
   const int4 rb = ix.root_box;
   int shx = 0, shy = 0;
   while (((1ll << kBinBits) << shx) < (long long)rb.y - rb.x) ++shx;
   while (((1ll << kBinBits) << shy) < (long long)rb.w - rb.z) ++shy;
+  const bool refine = shx >= kSubBits && shy >= kSubBits;
   hipLaunchKernelGGL(bin_zero_kernel, dim3(1), dim3(1024), 0, stream, tot);
   for (long long c0 = 0; c0 < n && e == hipSuccess; c0 += chunk) {
     const long long m = std::min(chunk, (long long)n - c0);
-    const long long per = (m + nblk - 1) / nblk;
+    const unsigned nblk = (unsigned)((m + kBinBlockPts - 1) / kBinBlockPts);
     mark(2);
-    hipLaunchKernelGGL(bin_count_kernel, dim3(nblk), dim3(1024), 0, stream, p + c0, m, per, rb, shx, shy, tot);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, stream, tot, cursor);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(nblk), dim3(1024), 0, stream, p + c0, m, per, rb, shx, shy, cursor,
-                       sorted, perm);
+    hipLaunchKernelGGL(bin_count_kernel, dim3(nblk), dim3(kBinThreads), 0, stream, p + c0, m, rb, shx, shy, tot);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kBinThreads), 0, stream, tot, cursor,
+                       refine ? pstart : nullptr);
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((m + kScatPts - 1) / kScatPts)), dim3(kBinThreads), 0,
+                       stream, p + c0, m, rb, shx, shy, cursor, sorted, perm);
+    if (refine)  // at most m / kRefPts + kBins pieces
+      hipLaunchKernelGGL(bin_refine_kernel, dim3((unsigned)(m / kRefPts + kBins)), dim3(kRefThreads), 0, stream,
+                         sorted, perm, cursor, pstart, rb, shx, shy);
     mark(0);
     switch (t.edge_chunk) {
       case 8: launch_sorted<3>(ix, sorted, perm, m, out + c0, t, num_cu, stream); break;
@@ -949,14 +1154,13 @@ hipError_t launch_count(const int32_t* ids, int64_t n, int32_t nb, unsigned long
     unsigned* cursor = tot + kBins;
     unsigned* part = cursor + kBins;
     int* sorted = reinterpret_cast<int*>(part + (size_t)ns * part_stride);
-    const int nblk = kBinBlocks;
-    const long long per = (n + nblk - 1) / nblk;
+    const unsigned nblk = (unsigned)((n + kBinBlockPts - 1) / kBinBlockPts);
     hipLaunchKernelGGL(bin_zero_kernel, dim3(1), dim3(1024), 0, stream, tot);
-    hipLaunchKernelGGL(cnt_bucket_count_kernel, dim3(nblk), dim3(1024), 0, stream, reinterpret_cast<const int*>(ids),
-                       (long long)n, nb, per, tot, counts);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, stream, tot, cursor);
-    hipLaunchKernelGGL(cnt_bucket_scatter_kernel, dim3(nblk), dim3(1024), 0, stream,
-                       reinterpret_cast<const int*>(ids), (long long)n, nb, per, cursor, sorted);
+    hipLaunchKernelGGL(cnt_bucket_count_kernel, dim3(nblk), dim3(kBinThreads), 0, stream,
+                       reinterpret_cast<const int*>(ids), (long long)n, nb, tot, counts);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kBinThreads), 0, stream, tot, cursor, nullptr);
+    hipLaunchKernelGGL(cnt_bucket_scatter_kernel, dim3(nblk), dim3(kBinThreads), 0, stream,
+                       reinterpret_cast<const int*>(ids), (long long)n, nb, cursor, sorted);
     hipLaunchKernelGGL(cnt_slice_kernel, dim3((unsigned)nbk, (unsigned)ns), dim3(1024), 0, stream, sorted, cursor, nb,
                        part, part_stride);
     const long long rb = std::min<long long>(((long long)nb + 255) / 256, (long long)num_cu * 8);
