@@ -103,9 +103,11 @@ struct BatchEntry {
 };
 
 // Calls of at least kPresortMin points are spatially sorted in chunks of
-// kPresortChunk points before mapping (when Tuning::presort is set).
+// kPresortChunk points before mapping (when Tuning::presort is set), up to
+// kPresortSuper points (all their chunks) per round of sort passes.
 constexpr long long kPresortMin = 1 << 20;
 constexpr long long kPresortChunk = 1 << 22;
+constexpr long long kPresortSuper = 1 << 27;
 
 struct Tuning {
   int edge_chunk;     // 4, 8 or 16

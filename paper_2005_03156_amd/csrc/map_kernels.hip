@@ -623,10 +623,14 @@ __device__ __forceinline__ void bin_load(const int2* __restrict__ xy, const long
 
 // Each block counts the bins of its range in LDS and adds the counts to the
 // chunk's per-bin totals.
-__global__ __launch_bounds__(kBinThreads) void bin_count_kernel(const int2* __restrict__ xy, const long long n,
-                                                                const int4 rb, const int shx, const int shy,
-                                                                unsigned* __restrict__ tot) {
+__global__ __launch_bounds__(kBinThreads) void bin_count_kernel(const int2* __restrict__ xy, const long long m,
+                                                                const long long chunk, const int4 rb, const int shx,
+                                                                const int shy, unsigned* __restrict__ tot) {
   __shared__ unsigned h[kBins];
+  const long long c0 = (long long)blockIdx.y * chunk, n = min(chunk, m - c0);
+  if ((long long)blockIdx.x * kBinBlockPts >= n) return;
+  xy += c0;
+  tot += (size_t)blockIdx.y * kBins;
   int2 p[kBinPer];
   unsigned b[kBinPer];
   bin_load(xy, n, rb, shx, shy, p, b);
@@ -647,14 +651,19 @@ constexpr int kRefThreads = 256;
 constexpr int kRefPer = 8;
 constexpr int kRefPts = kRefThreads * kRefPer;
 
-// cursor[bin] = first sorted position of the bin (exclusive scan of tot);
-// tot is cleared for the next chunk. With `pstart`, also the bins' first
-// piece numbers (exclusive scan of ceil(tot / kRefPts)) and, in
-// pstart[kBins], the number of pieces. One block of kBinThreads.
+constexpr int kPStride = kBins + 64;  // pstart entries per chunk
+
+// Block c handles chunk c. cursor[bin] = first sorted position of the bin in
+// the chunk (exclusive scan of tot); tot is cleared for the next use. With
+// `pstart`, also the bins' first piece numbers (exclusive scan of
+// ceil(tot / kRefPts)) and, in pstart[kBins], the number of pieces.
 __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(unsigned* __restrict__ tot,
                                                                unsigned* __restrict__ cursor,
                                                                unsigned* __restrict__ pstart) {
   constexpr int kPer = kBins / kBinThreads;
+  tot += (size_t)blockIdx.x * kBins;
+  cursor += (size_t)blockIdx.x * kBins;
+  if (pstart) pstart += (size_t)blockIdx.x * kPStride;
   __shared__ unsigned wsum[kBinThreads / kWave];
   unsigned v[kPer], mine = 0, pcs = 0;
 #pragma unroll
@@ -682,8 +691,9 @@ __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(unsigned* __restr
   }
 }
 
-__global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ tot) {
-  for (int i = threadIdx.x; i < kBins; i += blockDim.x) tot[i] = 0;
+__global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ tot, const long long count) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    tot[i] = 0;
 }
 
 // The scatter pass gives each block kScatPts points (kScatPer per thread).
@@ -696,16 +706,22 @@ __global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ t
 constexpr int kScatPer = 8;
 constexpr long long kScatPts = (long long)kBinThreads * kScatPer;
 
-__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __restrict__ xy, const long long n,
-                                                                  const int4 rb, const int shx, const int shy,
-                                                                  unsigned* __restrict__ cursor,
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __restrict__ xy, const long long m,
+                                                                  const long long chunk, const int4 rb, const int shx,
+                                                                  const int shy, unsigned* __restrict__ cursor,
                                                                   int2* __restrict__ sorted, int* __restrict__ perm) {
   __shared__ int2 sx[kScatPts];
   __shared__ unsigned short si[kScatPts];
   __shared__ unsigned h[kBins];  // counts, then first local position of each bin
-  __shared__ unsigned d[kBins];  // first global position minus first local position
+  __shared__ unsigned d[kBins];  // first position in the chunk minus first local position
   __shared__ unsigned wsum[kBinThreads / kWave];
+  const long long c0 = (long long)blockIdx.y * chunk, n = min(chunk, m - c0);
   const long long lo = (long long)blockIdx.x * kScatPts;
+  if (lo >= n) return;
+  xy += c0;
+  cursor += (size_t)blockIdx.y * kBins;
+  sorted += c0;
+  perm += c0;
   int2 p[kScatPer];
   unsigned b[kScatPer], r[kScatPer];
 #pragma unroll
@@ -755,8 +771,8 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   }
 }
 
-// Refinement: after the scatter, cursor[bin] is the end of the bin. Block i
-// takes piece i (the bin found by a binary search of pstart) and sorts its
+// Refinement: after the scatter, cursor[bin] is the end of the bin. Block
+// (i, c) takes piece i of chunk c (the bin found by a binary search of pstart) and sorts its
 // points and permutation entries in place by a 16 x 16 Morton sub-cell of the
 // bin's cell, through LDS. Bin and sub-cell together order the chunk along
 // a Z-curve on a 1024 x 1024 grid, so the mapping kernel's tiles of points
@@ -770,6 +786,7 @@ __device__ __forceinline__ unsigned sub_of(const int2 p, const int4 rb, const in
 }
 
 __global__ __launch_bounds__(kRefThreads) void bin_refine_kernel(int2* __restrict__ sorted, int* __restrict__ perm,
+                                                                 const long long chunk,
                                                                  const unsigned* __restrict__ cursor,
                                                                  const unsigned* __restrict__ pstart, const int4 rb,
                                                                  const int shx, const int shy) {
@@ -779,6 +796,10 @@ __global__ __launch_bounds__(kRefThreads) void bin_refine_kernel(int2* __restric
   __shared__ unsigned wsum[kRefThreads / kWave];
   __shared__ int the_bin;
   static_assert(kSubs == kRefThreads, "one sub-cell count per thread");
+  sorted += (long long)blockIdx.y * chunk;  // block (piece, chunk)
+  perm += (long long)blockIdx.y * chunk;
+  cursor += (size_t)blockIdx.y * kBins;
+  pstart += (size_t)blockIdx.y * kPStride;
   const unsigned piece = blockIdx.x;
   if (piece >= pstart[kBins]) return;
   if (threadIdx.x == 0) {  // the last bin whose first piece is <= piece
@@ -1057,43 +1078,53 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
     mark(1);
     return hipGetLastError();
   }
-  // spatially sorted, chunk by chunk, through stream-ordered scratch
+  // Spatially sorted through stream-ordered scratch (12 bytes per point, up
+  // to kPresortSuper points at a time): every sort pass runs once over all
+  // chunks of a super-chunk (chunk = blockIdx.y), then one mapping launch per
+  // chunk keeps its scattered result stores within the chunk's window.
   const long long chunk = std::min<long long>(n, kPresortChunk);
-  const size_t hist_bytes = sizeof(unsigned) * (3 * (size_t)kBins + 64);
-  const size_t bytes = hist_bytes + (size_t)chunk * (sizeof(int2) + sizeof(int)) + 256;
+  const long long super = std::min<long long>(n, kPresortSuper);
+  const long long max_nc = (super + chunk - 1) / chunk;
+  const size_t hist_bytes = (sizeof(unsigned) * (size_t)max_nc * (2 * (size_t)kBins + kPStride) + 255) / 256 * 256;
+  const size_t bytes = hist_bytes + (size_t)super * (sizeof(int2) + sizeof(int)) + 256;
   void* scratch = nullptr;
   hipError_t e = hipMallocAsync(&scratch, bytes, stream);
   if (e != hipSuccess) return e;
   unsigned* tot = static_cast<unsigned*>(scratch);
-  unsigned* cursor = tot + kBins;
-  unsigned* pstart = cursor + kBins;  // kBins + 1 entries
+  unsigned* cursor = tot + max_nc * kBins;
+  unsigned* pstart = cursor + max_nc * kBins;
   int2* sorted = reinterpret_cast<int2*>(static_cast<char*>(scratch) + hist_bytes);
-  int* perm = reinterpret_cast<int*>(sorted + chunk);
+  int* perm = reinterpret_cast<int*>(sorted + super);
   const int4 rb = ix.root_box;
   int shx = 0, shy = 0;
   while (((1ll << kBinBits) << shx) < (long long)rb.y - rb.x) ++shx;
   while (((1ll << kBinBits) << shy) < (long long)rb.w - rb.z) ++shy;
   const bool refine = shx >= kSubBits && shy >= kSubBits;
-  hipLaunchKernelGGL(bin_zero_kernel, dim3(1), dim3(1024), 0, stream, tot);
-  for (long long c0 = 0; c0 < n && e == hipSuccess; c0 += chunk) {
-    const long long m = std::min(chunk, (long long)n - c0);
-    const unsigned nblk = (unsigned)((m + kBinBlockPts - 1) / kBinBlockPts);
+  hipLaunchKernelGGL(bin_zero_kernel, dim3((unsigned)std::min<long long>(max_nc * 4, 1024)), dim3(1024), 0, stream,
+                     tot, max_nc * kBins);
+  for (long long s0 = 0; s0 < n && e == hipSuccess; s0 += super) {
+    const long long m = std::min(super, (long long)n - s0);  // the first super-chunk is the largest
+    const unsigned nc = (unsigned)((m + chunk - 1) / chunk);
     mark(2);
-    hipLaunchKernelGGL(bin_count_kernel, dim3(nblk), dim3(kBinThreads), 0, stream, p + c0, m, rb, shx, shy, tot);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kBinThreads), 0, stream, tot, cursor,
+    hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((chunk + kBinBlockPts - 1) / kBinBlockPts), nc),
+                       dim3(kBinThreads), 0, stream, p + s0, m, chunk, rb, shx, shy, tot);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(nc), dim3(kBinThreads), 0, stream, tot, cursor,
                        refine ? pstart : nullptr);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((m + kScatPts - 1) / kScatPts)), dim3(kBinThreads), 0,
-                       stream, p + c0, m, rb, shx, shy, cursor, sorted, perm);
-    if (refine)  // at most m / kRefPts + kBins pieces
-      hipLaunchKernelGGL(bin_refine_kernel, dim3((unsigned)(m / kRefPts + kBins)), dim3(kRefThreads), 0, stream,
-                         sorted, perm, cursor, pstart, rb, shx, shy);
-    mark(0);
-    switch (t.edge_chunk) {
-      case 8: launch_sorted<3>(ix, sorted, perm, m, out + c0, t, num_cu, stream); break;
-      case 16: launch_sorted<4>(ix, sorted, perm, m, out + c0, t, num_cu, stream); break;
-      default: launch_sorted<2>(ix, sorted, perm, m, out + c0, t, num_cu, stream); break;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc),
+                       dim3(kBinThreads), 0, stream, p + s0, m, chunk, rb, shx, shy, cursor, sorted, perm);
+    if (refine)  // at most chunk / kRefPts + kBins pieces per chunk
+      hipLaunchKernelGGL(bin_refine_kernel, dim3((unsigned)(chunk / kRefPts + kBins), nc), dim3(kRefThreads), 0,
+                         stream, sorted, perm, chunk, cursor, pstart, rb, shx, shy);
+    for (unsigned c = 0; c < nc; ++c) {
+      const long long c0 = (long long)c * chunk, mc = std::min(chunk, m - c0);
+      mark(0);
+      switch (t.edge_chunk) {
+        case 8: launch_sorted<3>(ix, sorted + c0, perm + c0, mc, out + s0 + c0, t, num_cu, stream); break;
+        case 16: launch_sorted<4>(ix, sorted + c0, perm + c0, mc, out + s0 + c0, t, num_cu, stream); break;
+        default: launch_sorted<2>(ix, sorted + c0, perm + c0, mc, out + s0 + c0, t, num_cu, stream); break;
+      }
+      mark(1);
     }
-    mark(1);
     e = hipGetLastError();
   }
   const hipError_t e2 = hipFreeAsync(scratch, stream);
@@ -1155,7 +1186,7 @@ hipError_t launch_count(const int32_t* ids, int64_t n, int32_t nb, unsigned long
     unsigned* part = cursor + kBins;
     int* sorted = reinterpret_cast<int*>(part + (size_t)ns * part_stride);
     const unsigned nblk = (unsigned)((n + kBinBlockPts - 1) / kBinBlockPts);
-    hipLaunchKernelGGL(bin_zero_kernel, dim3(1), dim3(1024), 0, stream, tot);
+    hipLaunchKernelGGL(bin_zero_kernel, dim3(4), dim3(1024), 0, stream, tot, (long long)kBins);
     hipLaunchKernelGGL(cnt_bucket_count_kernel, dim3(nblk), dim3(kBinThreads), 0, stream,
                        reinterpret_cast<const int*>(ids), (long long)n, nb, tot, counts);
     hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kBinThreads), 0, stream, tot, cursor, nullptr);

@@ -152,6 +152,13 @@ def test_grid221k_full_size_sampled_and_partition_property(torch_cuda, bm, grid2
     out2 = bm.map_points(ix, xy)
     torch.cuda.synchronize()
     assert torch.equal(out, out2)
+    # one call over more than 2^27 points: two rounds of sort passes, the
+    # second with a ragged last chunk
+    extra = 40_012_345
+    say("grid221k full size: one call of", n + extra)
+    out3 = bm.map_points(ix, torch.cat([xy, xy[:extra]]))
+    torch.cuda.synchronize()
+    assert torch.equal(out3[:n], out) and torch.equal(out3[n:], out[:extra])
 
 
 # ----------------------------------------------------- hard inputs ----
