@@ -252,6 +252,75 @@ __device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, c
   }
 }
 
+// The plain path keeps the (group, point) items of all levels in one ring,
+// S.item[0] (kCap entries), consumed 64 per round in FIFO order whatever
+// their level, so the rounds run full; (leaf, point) pairs go to S.item[1].
+// emit_ring appends to the ring at `tail`; slots [tail, lim) are free. Items
+// that do not fit mark their point for the depth-first fallback.
+__device__ __forceinline__ void emit_ring(WaveLds& S, bool pred, unsigned node, int plane, unsigned& tail,
+                                          const unsigned lim) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  const unsigned k = (unsigned)__popcll(m);
+  const unsigned slot = tail + lanes_below(m);
+  const unsigned it = (node << kSlotBits) | (unsigned)plane;
+  if (tail + k <= lim) {  // wave-uniform: every new item fits
+    if (pred) S.item[0][slot & (kCap - 1)] = it;
+  } else if (pred) {
+    if (slot < lim)
+      S.item[0][slot & (kCap - 1)] = it;
+    else
+      S.ovf[plane] = 1;
+  }
+  tail = min(tail + k, lim);
+}
+
+// As expand, for a round whose lanes may hold groups of different levels:
+// children that are leaves (the group's first child id is at least
+// leaf_base) become pairs, other children items of the ring.
+__device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
+                                             const int4 gb, const int2 pp, int pl, unsigned& tail,
+                                             const unsigned lim, unsigned& pcnt) {
+  const bool leaves = ci.x >= ix.leaf_base;
+  const char* rec = leaves ? reinterpret_cast<const char*>(ix.leaf) : reinterpret_cast<const char*>(ix.grp);
+  const unsigned sub = leaves ? (unsigned)ix.leaf_base : 0u;
+  const int shift = leaves ? 6 : 5;
+  const int m = has ? ci.y - ci.x : 0;
+  for (int base = 0; wave_any(base < m); base += 64) {
+    unsigned long long cand = 0ull;
+    if (base < m) {
+      const int mm = min(64, m - base);
+      cand = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
+      if (ci.z >= 0) {  // slot table (only groups of at most 64 children have one)
+        const int logS = ci.w & 0xff, shx = (ci.w >> 8) & 0xff, shy = (ci.w >> 16) & 0xff;
+        const unsigned S_ = 1u << logS;
+        const unsigned sx = ((unsigned)pp.x - (unsigned)gb.x) >> shx;
+        const unsigned sy = ((unsigned)pp.y - (unsigned)gb.z) >> shy;
+        if (pp.x < gb.x || pp.y < gb.z || sx >= S_ || sy >= S_)
+          cand = 0ull;
+        else
+          cand &= ix.slot_mask[(unsigned)ci.z + sx] & ix.slot_mask[(unsigned)ci.z + S_ + sy];
+      }
+    }
+    const unsigned c0 = (unsigned)(ci.x + base);
+    while (wave_any(cand != 0ull)) {
+      const bool h1 = cand != 0ull;
+      const unsigned n1 = h1 ? c0 + (unsigned)__builtin_ctzll(cand) : sub;
+      cand &= cand - 1ull;
+      const bool h2 = cand != 0ull;
+      const unsigned n2 = h2 ? c0 + (unsigned)__builtin_ctzll(cand) : sub;
+      cand &= cand - 1ull;
+      const int4 bx1 = *reinterpret_cast<const int4*>(rec + ((size_t)(n1 - sub) << shift));
+      const int4 bx2 = *reinterpret_cast<const int4*>(rec + ((size_t)(n2 - sub) << shift));
+      const bool in1 = h1 && in_box(bx1, pp), in2 = h2 && in_box(bx2, pp);
+      emit_ring(S, in1 && !leaves, n1, pl, tail, lim);
+      emit(S, 1, in1 && leaves, n1, pl, pcnt);
+      emit_ring(S, in2 && !leaves, n2, pl, tail, lim);
+      emit(S, 1, in2 && leaves, n2, pl, pcnt);
+    }
+  }
+}
+
 // Crossing-number test on the cnt (leaf, point) pairs of list `cur`, 64 pairs
 // per round; odd pairs atomic-min their block index into the point's slot of
 // S.best. A pair only needs the ring edges listed for the y-slab holding its
@@ -325,36 +394,29 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
   wave_sync();
 
   // ---- the root's children (level 0), one item per point
-  int cur = 0;
-  unsigned cnt = 0;
-  {
-    const LevelRecs L0 = level_recs(ix, ix.n_levels == 0);
+  static_assert((kCap & (kCap - 1)) == 0 && kCap >= 2 * kWave, "ring of a power-of-two size");
+  unsigned head = 0, tail = 0, pcnt = 0;
 #pragma unroll
-    for (int j = 0; j < kTilePts; ++j) {
-      const int i = j * kWave + lane;
-      expand(ix, S, i < nvalid, ix.root_child, ix.root_box, S.pts[i], i, cur, cnt, L0);
-    }
+  for (int j = 0; j < kTilePts; ++j) {
+    const int i = j * kWave + lane;
+    expand_mixed(ix, S, i < nvalid, ix.root_child, ix.root_box, S.pts[i], i, tail, head + kCap, pcnt);
   }
-  cnt = min(cnt, (unsigned)kCap);
   wave_sync();
 
-  // ---- lower levels: children of the surviving groups
-  for (int l = 0; l < ix.n_levels; ++l) {
-    const int nxt = cur ^ 1;
-    const LevelRecs L = level_recs(ix, l + 1 == ix.n_levels);
-    unsigned ncnt = 0;
-    for (unsigned r = 0; r < cnt; r += kWave) {
-      const unsigned q = r + lane;
-      const bool has = q < cnt;
-      const unsigned it = has ? S.item[cur][q] : 0u;  // lanes without an item read group 0
-      const GroupRec* g = ix.grp + (it >> kSlotBits);
-      const int pl = (int)(it & (kTile - 1));
-      expand(ix, S, has, g->child, g->box, S.pts[pl], pl, nxt, ncnt, L);
-    }
-    cnt = min(ncnt, (unsigned)kCap);
-    cur = nxt;
+  // ---- groups of every level, 64 items per round in FIFO order
+  while (head < tail) {
+    const unsigned q = head + lane;
+    const bool has = q < tail;
+    const unsigned it = has ? S.item[0][q & (kCap - 1)] : 0u;  // lanes without an item read group 0
+    head += min((unsigned)kWave, tail - head);
+    wave_sync();  // this round's slots are free from here on
+    const GroupRec* g = ix.grp + (it >> kSlotBits);
+    const int pl = (int)(it & (kTile - 1));
+    expand_mixed(ix, S, has, g->child, g->box, S.pts[pl], pl, tail, head + kCap, pcnt);
     wave_sync();
   }
+  const int cur = 1;
+  const unsigned cnt = min(pcnt, (unsigned)kCap);
 
   pip_rounds<kChunkShift>(ix, S, lane, cur, cnt);
 
