@@ -380,14 +380,39 @@ __device__ __forceinline__ void pip_rounds(const KIndex& ix, WaveLds& S, const i
 // candidate lists of a level hold the items of all of them, so its rounds of
 // 64 items run nearly full.
 template <int kChunkShift>
+__device__ __forceinline__ void map_tile_pts(const KIndex& ix, WaveLds& S, const int lane,
+                                             const int2 (&pt)[kTilePts], const int nvalid,
+                                             int* __restrict__ out, const int (&dst)[kTilePts],
+                                             const long long nperm);
+
+template <int kChunkShift>
 __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int lane,
                                          const int2* __restrict__ xy, const int nvalid,
                                          int* __restrict__ out, const int* __restrict__ perm = nullptr,
                                          const long long nperm = 0) {
+  int2 pt[kTilePts];
+  int dst[kTilePts];
 #pragma unroll
   for (int j = 0; j < kTilePts; ++j) {
     const int i = j * kWave + lane;
-    S.pts[i] = i < nvalid ? xy[i] : make_int2(0, 0);
+    pt[j] = i < nvalid ? xy[i] : make_int2(0, 0);
+    dst[j] = perm ? (i < nvalid ? perm[i] : -1) : i;
+  }
+  map_tile_pts<kChunkShift>(ix, S, lane, pt, nvalid, out, dst, perm ? nperm : (long long)nvalid);
+}
+
+// The tile's points given in registers (point j * 64 + lane in pt[j]); the
+// result of point j * 64 + lane < nvalid goes to out[dst[j]] when dst[j] lies
+// in [0, nperm).
+template <int kChunkShift>
+__device__ __forceinline__ void map_tile_pts(const KIndex& ix, WaveLds& S, const int lane,
+                                             const int2 (&pt)[kTilePts], const int nvalid,
+                                             int* __restrict__ out, const int (&dst)[kTilePts],
+                                             const long long nperm) {
+#pragma unroll
+  for (int j = 0; j < kTilePts; ++j) {
+    const int i = j * kWave + lane;
+    S.pts[i] = pt[j];
     S.best[i] = 0xFFFFFFFFu;
     S.ovf[i] = 0;
   }
@@ -426,10 +451,7 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
     if (i < nvalid) {
       unsigned best = S.best[i];
       if (S.ovf[i]) best = min(best, walk_point(ix, S.pts[i]));
-      if (!perm)
-        out[i] = (int)best;
-      else if ((unsigned long long)(long long)perm[i] < (unsigned long long)nperm)
-        out[perm[i]] = (int)best;
+      if ((unsigned long long)(long long)dst[j] < (unsigned long long)nperm) out[dst[j]] = (int)best;
     }
   }
   wave_sync();
@@ -921,10 +943,30 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void map_sorte
   WaveLds& S = wl[threadIdx.x / kWave];
   const long long ntiles = (n + kTile - 1) / kTile;
   const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
-  for (long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < ntiles;
-       t += nwaves) {
-    const long long i0 = t * kTile;
-    map_tile<kChunkShift>(ix, S, lane, xy + i0, (int)min((long long)kTile, n - i0), out, perm + i0, n);
+  // each wave loads its next tile's points and permutation entries while it
+  // maps the current one
+  int2 np[kTilePts];
+  int nq[kTilePts];
+  auto fetch = [&](const long long t) {
+#pragma unroll
+    for (int j = 0; j < kTilePts; ++j) {
+      const long long i = t * kTile + j * kWave + lane;
+      np[j] = i < n ? xy[i] : make_int2(0, 0);
+      nq[j] = i < n ? perm[i] : -1;
+    }
+  };
+  long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (t < ntiles) fetch(t);
+  for (; t < ntiles; t += nwaves) {
+    int2 pt[kTilePts];
+    int dst[kTilePts];
+#pragma unroll
+    for (int j = 0; j < kTilePts; ++j) {
+      pt[j] = np[j];
+      dst[j] = nq[j];
+    }
+    if (t + nwaves < ntiles) fetch(t + nwaves);
+    map_tile_pts<kChunkShift>(ix, S, lane, pt, (int)min((long long)kTile, n - t * kTile), out, dst, n);
   }
 }
 
