@@ -60,6 +60,20 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// Points, permutation entries and results are touched once per pass; they
+// are loaded (and the mapping kernels' results stored) non-temporally so that
+// they do not push the index's lines out of the caches (mapping kernel 5.60
+// -> 5.17 ms, sort passes 1.87 -> 1.68 ms per 100M points). The sort passes'
+// stores stay ordinary: their runs are merged in the caches.
+__device__ __forceinline__ int2 ld_once(const int2* p) {
+  int2 v;
+  v.x = __builtin_nontemporal_load(&p->x);
+  v.y = __builtin_nontemporal_load(&p->y);
+  return v;
+}
+__device__ __forceinline__ int ld_once(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_once(int* p, const int v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 __device__ __forceinline__ unsigned wave_incl_scan(unsigned v, int lane) {
@@ -395,8 +409,8 @@ __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int
 #pragma unroll
   for (int j = 0; j < kTilePts; ++j) {
     const int i = j * kWave + lane;
-    pt[j] = i < nvalid ? xy[i] : make_int2(0, 0);
-    dst[j] = perm ? (i < nvalid ? perm[i] : -1) : i;
+    pt[j] = i < nvalid ? ld_once(xy + i) : make_int2(0, 0);
+    dst[j] = perm ? (i < nvalid ? ld_once(perm + i) : -1) : i;
   }
   map_tile_pts<kChunkShift>(ix, S, lane, pt, nvalid, out, dst, perm ? nperm : (long long)nvalid);
 }
@@ -451,7 +465,7 @@ __device__ __forceinline__ void map_tile_pts(const KIndex& ix, WaveLds& S, const
     if (i < nvalid) {
       unsigned best = S.best[i];
       if (S.ovf[i]) best = min(best, walk_point(ix, S.pts[i]));
-      if ((unsigned long long)(long long)dst[j] < (unsigned long long)nperm) out[dst[j]] = (int)best;
+      if ((unsigned long long)(long long)dst[j] < (unsigned long long)nperm) st_once(out + dst[j], (int)best);
     }
   }
   wave_sync();
@@ -488,7 +502,7 @@ __device__ __forceinline__ void cover_tile(const KIndex& ix, const KCover& cv, W
 #pragma unroll
   for (int j = 0; j < kTilePts; ++j) {
     const int i = j * kWave + lane;
-    S.pts[i] = i < nvalid ? xy[i] : make_int2(0, 0);
+    S.pts[i] = i < nvalid ? ld_once(xy + i) : make_int2(0, 0);
     S.best[i] = 0xFFFFFFFFu;
     S.ovf[i] = 0;
   }
@@ -523,7 +537,7 @@ __device__ __forceinline__ void cover_tile(const KIndex& ix, const KCover& cv, W
     if (i < nvalid) {
       unsigned best = S.best[i];
       if (S.ovf[i]) best = min(best, walk_point(ix, S.pts[i]));
-      out[i] = (int)best;
+      st_once(out + i, (int)best);
     }
   }
   wave_sync();
@@ -698,7 +712,7 @@ __device__ __forceinline__ void bin_load(const int2* __restrict__ xy, const long
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k) {
     const long long i = lo + (long long)k * kBinThreads;
-    p[k] = i < n ? xy[i] : make_int2(0, 0);
+    p[k] = i < n ? ld_once(xy + i) : make_int2(0, 0);
   }
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k)
@@ -811,7 +825,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
 #pragma unroll
   for (int k = 0; k < kScatPer; ++k) {
     const long long i = lo + threadIdx.x + (long long)k * kBinThreads;
-    p[k] = i < n ? xy[i] : make_int2(0, 0);
+    p[k] = i < n ? ld_once(xy + i) : make_int2(0, 0);
   }
 #pragma unroll
   for (int k = 0; k < kScatPer; ++k)
@@ -906,8 +920,8 @@ __global__ __launch_bounds__(kRefThreads) void bin_refine_kernel(int2* __restric
 #pragma unroll
   for (int k = 0; k < kRefPer; ++k) {
     const int j = threadIdx.x + k * kRefThreads;
-    p[k] = j < cnt ? sorted[base + j] : make_int2(0, 0);
-    q[k] = j < cnt ? perm[base + j] : 0;
+    p[k] = j < cnt ? ld_once(sorted + base + j) : make_int2(0, 0);
+    q[k] = j < cnt ? ld_once(perm + base + j) : 0;
   }
 #pragma unroll
   for (int k = 0; k < kRefPer; ++k) {
@@ -951,8 +965,8 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void map_sorte
 #pragma unroll
     for (int j = 0; j < kTilePts; ++j) {
       const long long i = t * kTile + j * kWave + lane;
-      np[j] = i < n ? xy[i] : make_int2(0, 0);
-      nq[j] = i < n ? perm[i] : -1;
+      np[j] = i < n ? ld_once(xy + i) : make_int2(0, 0);
+      nq[j] = i < n ? ld_once(perm + i) : -1;
     }
   };
   long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
@@ -1016,7 +1030,7 @@ __device__ __forceinline__ void cnt_load(const int* __restrict__ ids, const long
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k) {
     const long long i = lo + (long long)k * kBinThreads;
-    id[k] = i < n ? ids[i] : -1;
+    id[k] = i < n ? ld_once(ids + i) : -1;
   }
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k)
