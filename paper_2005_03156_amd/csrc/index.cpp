@@ -24,7 +24,8 @@
 namespace bm {
 namespace {
 
-constexpr int kTableMinChildren = 6;  // below this a group's children are simply all tested
+constexpr int kTableMinChildren = 2;  // below this a group's children are simply all tested
+constexpr int kTableLogSlots = 5;     // slots per axis: 32
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 
@@ -35,8 +36,8 @@ inline void grow(int4& a, const int4& b) {
   a.w = std::max(a.w, b.w);
 }
 
-// Slot table of a group with 6..64 children: the group box is cut into S
-// equal power-of-two slots per axis (S = 8 up to 16 children, else 16), and
+// Slot table of a group with 2..64 children: the group box is cut into S = 32
+// equal power-of-two slots per axis, and
 // slot s of an axis holds a bit for every child whose box overlaps it on that
 // axis. For a point in the group box, (x-slot mask & y-slot mask) is a superset
 // of the children whose boxes contain it; the exact half-open box test is then
@@ -46,7 +47,7 @@ int4 make_table(BoxOf box_of, int c0, int c1, const int4& g, std::vector<uint64_
   int4 r = make_int4(c0, c1, -1, 0);
   const int m = c1 - c0;
   if (m < kTableMinChildren || m > 64 || g.x >= g.y || g.z >= g.w) return r;
-  const int logS = m <= 16 ? 3 : 4, S = 1 << logS;
+  const int logS = kTableLogSlots, S = 1 << logS;
   const int64_t wx = (int64_t)g.y - g.x, wy = (int64_t)g.w - g.z;
   int shx = 0, shy = 0;
   while (((int64_t)S << shx) < wx) ++shx;
@@ -376,7 +377,7 @@ bool consistent(const HostIndex& h) {
   auto table_ok = [&](const int4& c) {
     if (c.z < 0) return true;
     const int logS = c.w & 0xff, shx = (c.w >> 8) & 0xff, shy = (c.w >> 16) & 0xff, m = c.y - c.x;
-    if ((logS != 3 && logS != 4) || shx > 31 || shy > 31 || m < 1 || m > 64) return false;
+    if (logS < 3 || logS > 6 || shx > 31 || shy > 31 || m < 1 || m > 64) return false;
     const int64_t S = 1 << logS;
     if ((int64_t)c.z + 2 * S > (int64_t)h.slot_mask.size()) return false;
     const uint64_t keep = m == 64 ? ~0ull : ((1ull << m) - 1);
