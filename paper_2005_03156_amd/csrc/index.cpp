@@ -340,6 +340,7 @@ int make_device(HostIndex& h, bm_index** out) {
   k.g0 = h.g0;
   k.leaf_base = h.leaf_base;
   k.n_leaves = h.n_leaves;
+  k.presort_chunk = ix->bytes > kPresortBigIndex ? kPresortChunkBigIndex : kPresortChunk;
   ix->n_blocks = h.n_leaves;
   ix->n_nodes = (int64_t)h.parent.size();
   ix->n_verts = h.n_verts;

@@ -1200,7 +1200,7 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
   // to kPresortSuper points at a time): every sort pass runs once over all
   // chunks of a super-chunk (chunk = blockIdx.y), then one mapping launch per
   // chunk keeps its scattered result stores within the chunk's window.
-  const long long chunk = std::min<long long>(n, kPresortChunk);
+  const long long chunk = std::min<long long>(n, ix.presort_chunk);
   const long long super = std::min<long long>(n, kPresortSuper);
   const long long max_nc = (super + chunk - 1) / chunk;
   const size_t hist_bytes = (sizeof(unsigned) * (size_t)max_nc * (2 * (size_t)kBins + kPStride) + 255) / 256 * 256;

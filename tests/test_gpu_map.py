@@ -304,12 +304,15 @@ def test_quadtree8m_streamed_billion_points(torch_cuda, bm):
     N, CH = q["n_points"], q["chunk"]
     rng = np.random.default_rng(12)
     out = torch.empty(CH, dtype=torch.int32, device="cuda")
+    kept = []
     for k in range((N + CH - 1) // CH):
         n = min(CH, N - k * CH)
         pts = synth.points("quadtree8m", n, i0=k * CH)
         xy = torch.from_numpy(pts).cuda()
         bm.map_points(ix, xy, out[:n])
         got = out[:n].cpu().numpy()
+        if k < 2:
+            kept.append((xy, got))
         x, y = pts[:, 0], pts[:, 1]
         inside = (x >= 0) & (x < g.W) & (y >= 0) & (y < g.W)
         assert ((got >= 0) == inside).all(), k
@@ -318,6 +321,14 @@ def test_quadtree8m_streamed_billion_points(torch_cuda, bm):
         if k == 0:
             assert (got[:8_000_000] == H.map(pts[:8_000_000])).all()
         say("quadtree8m chunk", k, "ok", n)
+    # one call over two chunks and a ragged tail (2^27 + 12,345 points): with
+    # this index's size the sort runs in 2^26-point chunks, two rounds of sort
+    # passes
+    extra = 12_345
+    say("quadtree8m: one call of", 2 * CH + extra)
+    both = bm.map_points(ix, torch.cat([kept[0][0], kept[1][0], kept[0][0][:extra]])).cpu().numpy()
+    assert (both[:CH] == kept[0][1]).all() and (both[CH:2 * CH] == kept[1][1]).all()
+    assert (both[2 * CH:] == kept[0][1][:extra]).all()
 
 
 # ------------------------------------------------------- batched form ----
