@@ -74,7 +74,10 @@ typedef struct bm_index bm_index;
  *   parent        [n_levels] arrays: parent[l][i] in [0, n_groups[l]) is the
  *                 level-l group of entity i of level l+1 (of block i for
  *                 l = n_levels - 1). Groups may be empty. Any grouping gives
- *                 the same result; a spatially tight one is faster.
+ *                 the same result; a spatially tight one is faster. A level
+ *                 whose groups hold fewer than 4 entities on average is left
+ *                 out of the index (the level above adopts its entities)
+ *                 unless a group would then hold more than 256.
  *
  * The descriptor and its arrays are only read during bm_index_create. */
 typedef struct {
@@ -105,7 +108,7 @@ typedef struct {
   int64_t n_vertices;      /* ring vertices as given */
   int64_t n_nodes;         /* groups on all levels plus blocks */
   int64_t device_bytes;    /* device memory held by the index */
-  int32_t n_levels;        /* group levels */
+  int32_t n_levels;        /* group levels kept in the index */
   int32_t device;          /* HIP device ordinal holding the index */
   int64_t top_groups;      /* entities on the coarsest level */
 } bm_index_info;

@@ -22,7 +22,8 @@ namespace bm {
 struct alignas(32) GroupRec {
   int4 box;    // half-open (xmin, xmax, ymin, ymax), the union of the children's boxes
   int4 child;  // (first child, end of children, offset of the slot table in
-               // slot_mask or -1, log2 slot count | x shift << 8 | y shift << 16)
+               // slot_mask or -1, log2 slot count | x shift << 8 | y shift << 16 |
+               // words per slot row << 24)
 };
 
 // A block's ring is reached through y-slabs: its y-extent [ymin, ymax) is cut

@@ -24,8 +24,10 @@
 namespace bm {
 namespace {
 
-constexpr int kTableMinChildren = 2;  // below this a group's children are simply all tested
-constexpr int kTableLogSlots = 5;     // slots per axis: 32
+constexpr int kTableMinChildren = 2;    // below this a group's children are simply all tested
+constexpr int kTableMaxChildren = 256;  // above this too
+constexpr int kThinFanout = 4;          // group levels with fewer children per group are left out
+constexpr int kTableLogSlots = 5;       // slots per axis: 32
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 
@@ -36,36 +38,37 @@ inline void grow(int4& a, const int4& b) {
   a.w = std::max(a.w, b.w);
 }
 
-// Slot table of a group with 2..64 children: the group box is cut into S = 32
-// equal power-of-two slots per axis, and
-// slot s of an axis holds a bit for every child whose box overlaps it on that
-// axis. For a point in the group box, (x-slot mask & y-slot mask) is a superset
+// Slot table of a group with 2..256 children: the group box is cut into S = 32
+// equal power-of-two slots per axis, and the row of slot s of an axis (W =
+// ceil(children / 64) words) holds a bit for every child whose box overlaps it
+// on that axis; x-rows first, then y-rows. For a point in the group box, (x-slot mask & y-slot mask) is a superset
 // of the children whose boxes contain it; the exact half-open box test is then
 // run on those children only, so the filter's result is unchanged.
 template <class BoxOf>
 int4 make_table(BoxOf box_of, int c0, int c1, const int4& g, std::vector<uint64_t>& masks) {
   int4 r = make_int4(c0, c1, -1, 0);
   const int m = c1 - c0;
-  if (m < kTableMinChildren || m > 64 || g.x >= g.y || g.z >= g.w) return r;
-  const int logS = kTableLogSlots, S = 1 << logS;
+  if (m < kTableMinChildren || m > kTableMaxChildren || g.x >= g.y || g.z >= g.w) return r;
+  const int logS = kTableLogSlots, S = 1 << logS, W = (m + 63) / 64;
   const int64_t wx = (int64_t)g.y - g.x, wy = (int64_t)g.w - g.z;
   int shx = 0, shy = 0;
   while (((int64_t)S << shx) < wx) ++shx;
   while (((int64_t)S << shy) < wy) ++shy;
   const size_t off = masks.size();
-  if (off + 2 * S > (size_t)INT32_MAX) return r;
-  masks.resize(off + 2 * S, 0);
+  if (off + 2 * (size_t)S * W > (size_t)INT32_MAX) return r;
+  masks.resize(off + 2 * (size_t)S * W, 0);
   for (int c = c0; c < c1; ++c) {
     const int4 b = box_of(c);
     if (b.x >= b.y || b.z >= b.w) continue;  // an empty box holds no point
-    const uint64_t bit = 1ull << (c - c0);
+    const int w = (c - c0) >> 6;
+    const uint64_t bit = 1ull << ((c - c0) & 63);
     const int64_t sx0 = ((int64_t)b.x - g.x) >> shx, sx1 = ((int64_t)b.y - 1 - g.x) >> shx;
     const int64_t sy0 = ((int64_t)b.z - g.z) >> shy, sy1 = ((int64_t)b.w - 1 - g.z) >> shy;
-    for (int64_t t = sx0; t <= sx1; ++t) masks[off + t] |= bit;
-    for (int64_t t = sy0; t <= sy1; ++t) masks[off + S + t] |= bit;
+    for (int64_t t = sx0; t <= sx1; ++t) masks[off + t * W + w] |= bit;
+    for (int64_t t = sy0; t <= sy1; ++t) masks[off + (S + t) * W + w] |= bit;
   }
   r.z = (int)off;
-  r.w = logS | (shx << 8) | (shy << 16);
+  r.w = logS | (shx << 8) | (shy << 16) | (W << 24);
   return r;
 }
 
@@ -135,7 +138,7 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   if (B < 0 || B > INT32_MAX) return fail(BM_EINVAL, "bm_index_create: n_blocks out of range");
   if (d->n_levels < 0 || d->n_levels > 64) return fail(BM_EINVAL, "bm_index_create: n_levels out of range");
   if (B > 0 && (!d->vert_off || !d->verts_xy)) return fail(BM_EINVAL, "bm_index_create: null ring arrays");
-  const int L = d->n_levels;
+  int L = d->n_levels;
   if (L > 0 && (!d->n_groups || !d->parent)) return fail(BM_EINVAL, "bm_index_create: null hierarchy arrays");
 
   // level sizes, coarse to fine; the last level is the blocks
@@ -180,6 +183,37 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
                                    "] out of range");
   }
 
+  // Thin group levels are left out: a level whose groups hold fewer than
+  // kThinFanout children on average costs each point one more round of group
+  // items for little filtering, so the level above adopts its children (the
+  // root, for level 0). Group boxes are unions of their children's boxes, so
+  // the candidates stay a superset of the true hits and no result changes. A
+  // level stays if leaving it out would give a group more children than a
+  // slot table holds. (220,900-block grid with tracts of ~3 blocks: mapping
+  // kernel 5.03 -> 4.70 ms per 100M points.)
+  std::vector<const int32_t*> par(d->parent, d->parent + L);
+  std::vector<std::vector<int32_t>> composed;
+  composed.reserve(L);
+  for (int l = L - 1; l >= 0; --l) {
+    const int64_t G = size[l], E = size[l + 1];
+    if (E >= kThinFanout * G) continue;
+    if (l == 0) {
+      if (E > kTableMaxChildren) continue;
+    } else {
+      std::vector<int32_t> cnt(size[l - 1], 0);
+      bool fits = true;
+      for (int64_t e = 0; e < E && fits; ++e) fits = ++cnt[par[l - 1][par[l][e]]] <= kTableMaxChildren;
+      if (!fits) continue;
+      composed.emplace_back(E);
+      for (int64_t e = 0; e < E; ++e) composed.back()[e] = par[l - 1][par[l][e]];
+      par[l - 1] = composed.back().data();
+    }
+    par.erase(par.begin() + l);
+    size.erase(size.begin() + l);
+    total_nodes -= G;
+    --L;
+  }
+
   // new positions: level 0 keeps its order; a finer level is sorted stably by
   // the new position of its parent
   std::vector<int64_t> base(L + 2, 0);
@@ -195,10 +229,10 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   h.grp.assign(base[L], GroupRec{kEmptyBox, make_int4(0, 0, -1, 0)});
   h.parent.assign(total_nodes, -1);
   for (int l = 0; l < L; ++l) {
-    const int32_t* par = d->parent[l];
+    const int32_t* pl = par[l];
     const int64_t G = size[l], E = size[l + 1];
     std::vector<int64_t> cnt(G + 1, 0);
-    for (int64_t e = 0; e < E; ++e) cnt[pos[l][par[e]] + 1]++;
+    for (int64_t e = 0; e < E; ++e) cnt[pos[l][pl[e]] + 1]++;
     for (int64_t g = 0; g < G; ++g) cnt[g + 1] += cnt[g];
     for (int64_t g = 0; g < G; ++g)  // children of the group at new position g
       h.grp[base[l] + g].child =
@@ -207,10 +241,10 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
     if (l + 1 == L) leaf_order.resize(E);
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
     for (int64_t e = 0; e < E; ++e) {
-      const int64_t np = fill[pos[l][par[e]]]++;
+      const int64_t np = fill[pos[l][pl[e]]]++;
       pos[l + 1][e] = (int32_t)np;
       if (l + 1 == L) leaf_order[np] = (int32_t)e;
-      h.parent[base[l + 1] + np] = (int32_t)(base[l] + pos[l][par[e]]);
+      h.parent[base[l + 1] + np] = (int32_t)(base[l] + pos[l][pl[e]]);
     }
   }
 
@@ -378,12 +412,17 @@ bool consistent(const HostIndex& h) {
   auto table_ok = [&](const int4& c) {
     if (c.z < 0) return true;
     const int logS = c.w & 0xff, shx = (c.w >> 8) & 0xff, shy = (c.w >> 16) & 0xff, m = c.y - c.x;
-    if (logS < 3 || logS > 6 || shx > 31 || shy > 31 || m < 1 || m > 64) return false;
+    const int W = (int)((unsigned)c.w >> 24);
+    if (logS < 3 || logS > 6 || shx > 31 || shy > 31 || m < 1 || m > kTableMaxChildren || W != (m + 63) / 64)
+      return false;
     const int64_t S = 1 << logS;
-    if ((int64_t)c.z + 2 * S > (int64_t)h.slot_mask.size()) return false;
-    const uint64_t keep = m == 64 ? ~0ull : ((1ull << m) - 1);
+    if ((int64_t)c.z + 2 * S * W > (int64_t)h.slot_mask.size()) return false;
     for (int64_t t = 0; t < 2 * S; ++t)
-      if (h.slot_mask[c.z + t] & ~keep) return false;
+      for (int w = 0; w < W; ++w) {
+        const int left = m - 64 * w;  // children in word w
+        const uint64_t keep = left >= 64 ? ~0ull : ((1ull << left) - 1);
+        if (h.slot_mask[c.z + t * W + w] & ~keep) return false;
+      }
     return true;
   };
   for (int64_t g = 0; g < lb; ++g) {

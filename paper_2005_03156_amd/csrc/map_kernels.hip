@@ -222,50 +222,6 @@ __device__ __forceinline__ LevelRecs level_recs(const KIndex& ix, const bool lea
   return L;
 }
 
-// Children of one group per lane (ci = child record, gb = group box, pp =
-// the lane's point): every child whose half-open box holds pp is appended to
-// list `dst`. With a slot table only the children flagged in both the x-slot
-// and the y-slot of pp are tested; otherwise all of them, 64 at a time.
-// Called with all 64 lanes active; `has` masks lanes without an item.
-__device__ __forceinline__ void expand(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
-                                       const int4 gb, const int2 pp, int pl, int dst, unsigned& cnt,
-                                       const LevelRecs L) {
-  const int m = has ? ci.y - ci.x : 0;
-  for (int base = 0; wave_any(base < m); base += 64) {
-    unsigned long long cand = 0ull;
-    if (base < m) {
-      const int mm = min(64, m - base);
-      cand = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
-      if (ci.z >= 0) {  // slot table (only groups of at most 64 children have one)
-        const int logS = ci.w & 0xff, shx = (ci.w >> 8) & 0xff, shy = (ci.w >> 16) & 0xff;
-        const unsigned S_ = 1u << logS;
-        // exact offsets once pp is known to lie at or above the box's low corner
-        const unsigned sx = ((unsigned)pp.x - (unsigned)gb.x) >> shx;
-        const unsigned sy = ((unsigned)pp.y - (unsigned)gb.z) >> shy;
-        if (pp.x < gb.x || pp.y < gb.z || sx >= S_ || sy >= S_)
-          cand = 0ull;
-        else
-          cand &= ix.slot_mask[(unsigned)ci.z + sx] & ix.slot_mask[(unsigned)ci.z + S_ + sy];
-      }
-    }
-    const unsigned c0 = (unsigned)(ci.x + base);
-    while (wave_any(cand != 0ull)) {
-      const bool h1 = cand != 0ull;
-      const unsigned n1 = h1 ? c0 + (unsigned)__builtin_ctzll(cand) : L.sub;
-      cand &= cand - 1ull;
-      const bool h2 = cand != 0ull;
-      const unsigned n2 = h2 ? c0 + (unsigned)__builtin_ctzll(cand) : L.sub;
-      cand &= cand - 1ull;
-      // both loads are issued before either box is used; a lane without a
-      // candidate reads the level's first record
-      const int4 bx1 = *reinterpret_cast<const int4*>(L.rec + ((size_t)(n1 - L.sub) << L.shift));
-      const int4 bx2 = *reinterpret_cast<const int4*>(L.rec + ((size_t)(n2 - L.sub) << L.shift));
-      emit(S, dst, h1 && in_box(bx1, pp), n1, pl, cnt);
-      emit(S, dst, h2 && in_box(bx2, pp), n2, pl, cnt);
-    }
-  }
-}
-
 // The plain path keeps the (group, point) items of all levels in one ring,
 // S.item[0] (kCap entries), consumed 64 per round in FIFO order whatever
 // their level, so the rounds run full; (leaf, point) pairs go to S.item[1].
@@ -289,9 +245,14 @@ __device__ __forceinline__ void emit_ring(WaveLds& S, bool pred, unsigned node, 
   tail = min(tail + k, lim);
 }
 
-// As expand, for a round whose lanes may hold groups of different levels:
-// children that are leaves (the group's first child id is at least
-// leaf_base) become pairs, other children items of the ring.
+// Children of one group per lane (ci = child record, gb = group box, pp =
+// the lane's point), in a round whose lanes may hold groups of different
+// levels: every child whose half-open box holds pp is emitted; children that
+// are leaves (the group's first child id is at least leaf_base) become pairs,
+// other children items of the ring. With a slot table only the children
+// flagged in both the x-slot and the y-slot of pp are tested (a table row
+// holds one 64-bit word per 64 children); otherwise all of them, 64 at a
+// time. Called with all 64 lanes active; `has` masks lanes without an item.
 __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
                                              const int4 gb, const int2 pp, int pl, unsigned& tail,
                                              const unsigned lim, unsigned& pcnt) {
@@ -305,15 +266,18 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
     if (base < m) {
       const int mm = min(64, m - base);
       cand = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
-      if (ci.z >= 0) {  // slot table (only groups of at most 64 children have one)
+      if (ci.z >= 0) {  // slot table: S x-rows then S y-rows of W words
         const int logS = ci.w & 0xff, shx = (ci.w >> 8) & 0xff, shy = (ci.w >> 16) & 0xff;
+        const unsigned W = (unsigned)ci.w >> 24;
         const unsigned S_ = 1u << logS;
         const unsigned sx = ((unsigned)pp.x - (unsigned)gb.x) >> shx;
         const unsigned sy = ((unsigned)pp.y - (unsigned)gb.z) >> shy;
-        if (pp.x < gb.x || pp.y < gb.z || sx >= S_ || sy >= S_)
+        if (pp.x < gb.x || pp.y < gb.z || sx >= S_ || sy >= S_) {
           cand = 0ull;
-        else
-          cand &= ix.slot_mask[(unsigned)ci.z + sx] & ix.slot_mask[(unsigned)ci.z + S_ + sy];
+        } else {
+          const unsigned w = (unsigned)base >> 6;
+          cand &= ix.slot_mask[(unsigned)ci.z + sx * W + w] & ix.slot_mask[(unsigned)ci.z + (S_ + sy) * W + w];
+        }
       }
     }
     const unsigned c0 = (unsigned)(ci.x + base);

@@ -219,6 +219,23 @@ def test_random_hierarchies_and_empty_groups(torch_cuda, bm):
     assert (gpu_map(bm, torch_cuda, ix, pts) == want).all()
 
 
+@pytest.mark.parametrize("per_group", [65, 100, 200, 256, 257])
+def test_wide_groups(torch_cuda, bm, per_group):
+    """Groups of 65..256 children use slot tables with several 64-bit words per
+    row; 257 and more have none. Children in id order (row strips) and
+    scattered at random."""
+    g = synth.geometry("grid1k")
+    pts = np.concatenate([synth.points("grid1k", 20000), boundary_points(g, 500)])
+    want = oracle.brute(g.vert_off, g.verts, pts)
+    rng = np.random.default_rng(per_group)
+    for name, order in [("strips", np.arange(g.n_blocks)), ("scattered", rng.permutation(g.n_blocks))]:
+        parent = np.empty(g.n_blocks, np.int32)
+        parent[order] = np.arange(g.n_blocks) // per_group
+        say("wide groups", per_group, name)
+        ix = bm.Index(g.vert_off, g.verts, [int(parent.max()) + 1], [parent])
+        assert (gpu_map(bm, torch_cuda, ix, pts) == want).all()
+
+
 def test_overlapping_blocks_smallest_id(torch_cuda, bm):
     say("overlaps")
     rng = np.random.default_rng(6)

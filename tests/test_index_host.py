@@ -67,7 +67,12 @@ def grid221k_index(tmp_path_factory):
 def test_structure_and_boxes(grid221k_index):
     g, ix = grid221k_index
     B, lb = ix["n_leaves"], ix["leaf_base"]
-    assert B == g.n_blocks and lb == sum(g.n_groups) and ix["g0"] == g.n_groups[0]
+    # the tract level (about 3 blocks per tract) is left out: each county holds
+    # the blocks of its tracts
+    assert B == g.n_blocks and lb == g.n_groups[0] + g.n_groups[1] and ix["g0"] == g.n_groups[0]
+    county_of_block = g.parents[1][g.parents[2]]
+    per_county = ix["child"][g.n_groups[0]:lb, 1] - ix["child"][g.n_groups[0]:lb, 0]
+    assert np.array_equal(np.sort(per_county), np.sort(np.bincount(county_of_block, minlength=g.n_groups[1])))
     assert ix["n_verts"] == g.verts.shape[0]
     # leaf ids are a permutation; leaf boxes are the ring extents (oracle's own)
     lid = ix["leaf"]["leaf_id"]
@@ -87,14 +92,39 @@ def test_structure_and_boxes(grid221k_index):
     assert np.all(starts[1:] >= starts[:-1])
 
 
+@pytest.mark.parametrize("top, kept", [(4, False), (2, True)])
+def test_thin_levels(tmp_path, top, kept):
+    """A group level whose groups hold fewer than 4 children on average is left
+    out (its parents adopt the children) unless a parent would then hold more
+    than 256 children. 1,024 blocks in 400 groups of ~2.6 under `top` groups:
+    with 4 top groups each adopts 256 blocks; with 2 each would get 512."""
+    import paper_2005_03156_amd as bm
+    g = synth.geometry("grid1k")
+    mid = (np.arange(g.n_blocks) * 400 // g.n_blocks).astype(np.int32)
+    up = (np.arange(400) * top // 400).astype(np.int32)
+    p = str(tmp_path / "t.bmi")
+    bm.build_index_file(p, g.vert_off, g.verts, [top, 400], [up, mid])
+    ix = read_index(p)
+    assert ix["g0"] == top and ix["leaf_base"] == (top + 400 if kept else top)
+    child = ix["child"][:top]
+    if not kept:
+        assert np.all(child[:, 1] - child[:, 0] == g.n_blocks // top) and np.all(child[:, 0] >= top)
+        assert np.all(child[:, 2] >= 0)  # 256 children: still a slot table
+
+
 def _table_candidates(ix, crec, gbox, px, py):
+    """Candidate set of a point from a group's slot table, as one Python int
+    (bit k = child k): x-rows then y-rows of W words each."""
     c0, c1, off, packed = (int(v) for v in crec)
-    logS, shx, shy = packed & 0xFF, (packed >> 8) & 0xFF, (packed >> 16) & 0xFF
+    logS, shx, shy, W = packed & 0xFF, (packed >> 8) & 0xFF, (packed >> 16) & 0xFF, (packed >> 24) & 0xFF
+    assert W == (c1 - c0 + 63) // 64
     S = 1 << logS
     sx, sy = (px - int(gbox[0])) >> shx, (py - int(gbox[2])) >> shy
     if not (0 <= sx < S and 0 <= sy < S):
         return 0
-    return int(ix["slot_mask"][off + sx]) & int(ix["slot_mask"][off + S + sy])
+    mx = sum(int(ix["slot_mask"][off + sx * W + w]) << (64 * w) for w in range(W))
+    my = sum(int(ix["slot_mask"][off + (S + sy) * W + w]) << (64 * w) for w in range(W))
+    return mx & my
 
 
 def test_slot_tables_are_supersets(grid221k_index):
@@ -116,6 +146,40 @@ def test_slot_tables_are_supersets(grid221k_index):
             for k in np.flatnonzero(inside):
                 assert cand >> int(k) & 1
             assert cand >> (c1 - c0) == 0
+
+
+def _check_tables(ix, groups, rng, tries=40):
+    for crec, gb in groups:
+        c0, c1 = int(crec[0]), int(crec[1])
+        assert int(crec[2]) >= 0
+        for _ in range(tries):
+            px = int(rng.integers(gb[0], gb[1]))
+            py = int(rng.integers(gb[2], gb[3]))
+            cand = _table_candidates(ix, crec, gb, px, py)
+            cb = ix["box"][c0:c1]
+            inside = (cb[:, 0] <= px) & (px < cb[:, 1]) & (cb[:, 2] <= py) & (py < cb[:, 3])
+            for k in np.flatnonzero(inside):
+                assert cand >> int(k) & 1
+            assert cand >> (c1 - c0) == 0
+
+
+@pytest.mark.parametrize("per_group", [200, 1024])
+def test_slot_tables_with_several_words_per_row(tmp_path, per_group):
+    """Groups of 65..256 children keep a table whose rows hold one 64-bit word
+    per 64 children; larger groups have none (their children are all tested)."""
+    import paper_2005_03156_amd as bm
+    g = synth.geometry("grid1k")
+    parent = (np.arange(g.n_blocks) // per_group).astype(np.int32)
+    ng = int(parent.max()) + 1
+    p = str(tmp_path / "w.bmi")
+    bm.build_index_file(p, g.vert_off, g.verts, [ng], [parent])
+    ix = read_index(p)
+    child = ix["child"][:ng]
+    m = child[:, 1] - child[:, 0]
+    has = child[:, 2] >= 0
+    assert np.array_equal(has, (m >= 2) & (m <= 256))
+    rng = np.random.default_rng(per_group)
+    _check_tables(ix, [(child[k], ix["box"][k]) for k in np.flatnonzero(has)], rng, tries=300)
 
 
 def test_y_slabs_list_every_straddling_edge(grid221k_index):
