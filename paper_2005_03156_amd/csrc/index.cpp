@@ -375,6 +375,7 @@ int make_device(HostIndex& h, bm_index** out) {
   k.leaf_base = h.leaf_base;
   k.n_leaves = h.n_leaves;
   k.presort_chunk = ix->bytes > kPresortBigIndex ? kPresortChunkBigIndex : kPresortChunk;
+  k.presort_bin_bits = ix->bytes > kPresortBigIndex ? 6 : 5;
   ix->n_blocks = h.n_leaves;
   ix->n_nodes = (int64_t)h.parent.size();
   ix->n_verts = h.n_verts;

@@ -611,13 +611,22 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map
 // Points arrive in any order; a wave maps 64 of them together, and its tree
 // nodes, slab lists and cache lines are shared only when those points are
 // close. Before mapping, each chunk of points is therefore counting-sorted by
-// a 12-bit key: the Morton index of its cell in a 64 x 64 grid over the root
-// box (points outside fall in the nearest border cell). The mapping kernel
-// then reads the sorted copy and writes each result back to the point's
-// original position. Each point's result depends on that point alone, so the
-// order does not change any output.
-constexpr int kBinBits = 6;  // per axis
-constexpr int kBins = 1 << (2 * kBinBits);
+// the Morton index of its cell in a 2^kBB x 2^kBB grid of bins over the root
+// box (points outside fall in the nearest border cell), and each bin is then
+// re-sorted by a 2^(10-kBB) x 2^(10-kBB) grid of sub-cells: together a
+// Z-order on a 1024 x 1024 grid. The mapping kernel then reads the sorted
+// copy and writes each result back to the point's original position. Each
+// point's result depends on that point alone, so the order does not change
+// any output. kBB is 5 for an index that fits the last-level cache (shorter
+// sort passes) and 6 for a larger one (tighter bins, fewer index re-reads).
+template <int kBB>
+struct Bins {
+  static constexpr int kN = 1 << (2 * kBB);          // bins
+  static constexpr int kSubBits = 10 - kBB;          // per axis
+  static constexpr int kSubs = 1 << (2 * kSubBits);  // sub-cells per bin
+  static constexpr int kRefPer = kBB == 5 ? 16 : 8;  // refinement: points per thread
+};
+constexpr int kBins = 1 << 12;  // the most bins of any grid: per-chunk stride of the bin arrays
 constexpr int kBinThreads = 1024;  // threads per block of the count and scatter passes
 constexpr int kBinPer = 16;        // points per thread: all loaded before any LDS atomic
 constexpr long long kBinBlockPts = (long long)kBinThreads * kBinPer;
@@ -630,9 +639,10 @@ __device__ __forceinline__ unsigned spread6(unsigned v) {
   return v;
 }
 
+template <int kBB>
 __device__ __forceinline__ unsigned bin_of(const int2 p, const int4 rb, const int shx, const int shy) {
   const long long dx = (long long)p.x - rb.x, dy = (long long)p.y - rb.z;
-  const long long top = (1 << kBinBits) - 1;
+  const long long top = (1 << kBB) - 1;
   const unsigned cx = (unsigned)min(top, max(0ll, dx >> shx));
   const unsigned cy = (unsigned)min(top, max(0ll, dy >> shy));
   return spread6(cx) | (spread6(cy) << 1);
@@ -669,6 +679,7 @@ __device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* w
 // thread t the points t, t + kBinThreads, ... of that range, and load all of a
 // thread's points before the first LDS atomic, so the loads of a block are in
 // flight together rather than one per loop trip.
+template <int kBB>
 __device__ __forceinline__ void bin_load(const int2* __restrict__ xy, const long long n, const int4 rb,
                                          const int shx, const int shy, int2 (&p)[kBinPer],
                                          unsigned (&b)[kBinPer]) {
@@ -680,49 +691,49 @@ __device__ __forceinline__ void bin_load(const int2* __restrict__ xy, const long
   }
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k)
-    b[k] = lo + (long long)k * kBinThreads < n ? bin_of(p[k], rb, shx, shy) : (unsigned)kBins;
+    b[k] = lo + (long long)k * kBinThreads < n ? bin_of<kBB>(p[k], rb, shx, shy) : (unsigned)Bins<kBB>::kN;
 }
 
 // Each block counts the bins of its range in LDS and adds the counts to the
 // chunk's per-bin totals.
+template <int kBB>
 __global__ __launch_bounds__(kBinThreads) void bin_count_kernel(const int2* __restrict__ xy, const long long m,
                                                                 const long long chunk, const int4 rb, const int shx,
                                                                 const int shy, unsigned* __restrict__ tot) {
-  __shared__ unsigned h[kBins];
+  constexpr int kNB = Bins<kBB>::kN;
+  __shared__ unsigned h[kNB];
   const long long c0 = (long long)blockIdx.y * chunk, n = min(chunk, m - c0);
   if ((long long)blockIdx.x * kBinBlockPts >= n) return;
   xy += c0;
   tot += (size_t)blockIdx.y * kBins;
   int2 p[kBinPer];
   unsigned b[kBinPer];
-  bin_load(xy, n, rb, shx, shy, p, b);
-  for (int i = threadIdx.x; i < kBins; i += kBinThreads) h[i] = 0;
+  bin_load<kBB>(xy, n, rb, shx, shy, p, b);
+  for (int i = threadIdx.x; i < kNB; i += kBinThreads) h[i] = 0;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k)
-    if (b[k] < (unsigned)kBins) atomicAdd(&h[b[k]], 1u);
+    if (b[k] < (unsigned)kNB) atomicAdd(&h[b[k]], 1u);
   __syncthreads();
-  for (int i = threadIdx.x; i < kBins; i += kBinThreads)
+  for (int i = threadIdx.x; i < kNB; i += kBinThreads)
     if (h[i]) atomicAdd(&tot[i], h[i]);
 }
 
-// The refinement pass cuts every bin into pieces of kRefPts points.
-constexpr int kSubBits = 4;  // per axis: 16 x 16 sub-cells per bin
-constexpr int kSubs = 1 << (2 * kSubBits);
+// The refinement pass cuts every bin into pieces of kRefThreads * kRefPer points.
 constexpr int kRefThreads = 256;
-constexpr int kRefPer = 8;
-constexpr int kRefPts = kRefThreads * kRefPer;
 
 constexpr int kPStride = kBins + 64;  // pstart entries per chunk
 
 // Block c handles chunk c. cursor[bin] = first sorted position of the bin in
 // the chunk (exclusive scan of tot); tot is cleared for the next use. With
 // `pstart`, also the bins' first piece numbers (exclusive scan of
-// ceil(tot / kRefPts)) and, in pstart[kBins], the number of pieces.
+// ceil(tot / piece size)) and, in pstart[kN], the number of pieces.
+template <int kBB>
 __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(unsigned* __restrict__ tot,
                                                                unsigned* __restrict__ cursor,
                                                                unsigned* __restrict__ pstart) {
-  constexpr int kPer = kBins / kBinThreads;
+  constexpr int kNB = Bins<kBB>::kN, kPer = kNB / kBinThreads;
+  constexpr unsigned kRefPts = kRefThreads * Bins<kBB>::kRefPer;
   tot += (size_t)blockIdx.x * kBins;
   cursor += (size_t)blockIdx.x * kBins;
   if (pstart) pstart += (size_t)blockIdx.x * kPStride;
@@ -749,7 +760,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(unsigned* __restr
       pstart[threadIdx.x * kPer + k] = pr;
       pr += (v[k] + kRefPts - 1) / kRefPts;
     }
-    if (threadIdx.x == kBinThreads - 1) pstart[kBins] = pr;
+    if (threadIdx.x == kBinThreads - 1) pstart[kNB] = pr;
   }
 }
 
@@ -768,14 +779,16 @@ __global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ t
 constexpr int kScatPer = 8;
 constexpr long long kScatPts = (long long)kBinThreads * kScatPer;
 
+template <int kBB>
 __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __restrict__ xy, const long long m,
                                                                   const long long chunk, const int4 rb, const int shx,
                                                                   const int shy, unsigned* __restrict__ cursor,
                                                                   int2* __restrict__ sorted, int* __restrict__ perm) {
   __shared__ int2 sx[kScatPts];
   __shared__ unsigned short si[kScatPts];
-  __shared__ unsigned h[kBins];  // counts, then first local position of each bin
-  __shared__ unsigned d[kBins];  // first position in the chunk minus first local position
+  constexpr int kNB = Bins<kBB>::kN;
+  __shared__ unsigned h[kNB];  // counts, then first local position of each bin
+  __shared__ unsigned d[kNB];  // first position in the chunk minus first local position
   __shared__ unsigned wsum[kBinThreads / kWave];
   const long long c0 = (long long)blockIdx.y * chunk, n = min(chunk, m - c0);
   const long long lo = (long long)blockIdx.x * kScatPts;
@@ -793,14 +806,14 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   }
 #pragma unroll
   for (int k = 0; k < kScatPer; ++k)
-    b[k] = lo + threadIdx.x + (long long)k * kBinThreads < n ? bin_of(p[k], rb, shx, shy) : (unsigned)kBins;
-  for (int i = threadIdx.x; i < kBins; i += kBinThreads) h[i] = 0;
+    b[k] = lo + threadIdx.x + (long long)k * kBinThreads < n ? bin_of<kBB>(p[k], rb, shx, shy) : (unsigned)kNB;
+  for (int i = threadIdx.x; i < kNB; i += kBinThreads) h[i] = 0;
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kScatPer; ++k) r[k] = b[k] < (unsigned)kBins ? atomicAdd(&h[b[k]], 1u) : 0u;
+  for (int k = 0; k < kScatPer; ++k) r[k] = b[k] < (unsigned)kNB ? atomicAdd(&h[b[k]], 1u) : 0u;
   __syncthreads();
   // local starts (exclusive scan of the counts) and the global runs
-  constexpr int kQ = kBins / kBinThreads;
+  constexpr int kQ = kNB / kBinThreads;
   unsigned v[kQ], mine = 0;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
@@ -818,7 +831,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kScatPer; ++k)
-    if (b[k] < (unsigned)kBins) {
+    if (b[k] < (unsigned)kNB) {
       const unsigned j = h[b[k]] + r[k];
       sx[j] = p[k];
       si[j] = (unsigned short)(threadIdx.x + k * kBinThreads);
@@ -827,7 +840,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   const int cnt = (int)min((long long)kScatPts, n - lo);
   for (int j = threadIdx.x; j < cnt; j += kBinThreads) {
     const int2 q = sx[j];
-    const unsigned pos = d[bin_of(q, rb, shx, shy)] + (unsigned)j;
+    const unsigned pos = d[bin_of<kBB>(q, rb, shx, shy)] + (unsigned)j;
     sorted[pos] = q;
     perm[pos] = (int)(lo + si[j]);
   }
@@ -835,44 +848,50 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
 
 // Refinement: after the scatter, cursor[bin] is the end of the bin. Block
 // (i, c) takes piece i of chunk c (the bin found by a binary search of pstart) and sorts its
-// points and permutation entries in place by a 16 x 16 Morton sub-cell of the
-// bin's cell, through LDS. Bin and sub-cell together order the chunk along
+// points and permutation entries in place by the Morton index of their
+// sub-cell of the bin's cell, through LDS. Bin and sub-cell together order the chunk along
 // a Z-curve on a 1024 x 1024 grid, so the mapping kernel's tiles of points
 // are spatially tighter. Blocks beyond the last piece exit at once.
+template <int kBB>
 __device__ __forceinline__ unsigned sub_of(const int2 p, const int4 rb, const int shx, const int shy) {
+  constexpr int kSubBits = Bins<kBB>::kSubBits;
   const long long dx = (long long)p.x - rb.x, dy = (long long)p.y - rb.z;
-  const long long top = (1ll << (kBinBits + kSubBits)) - 1;
+  const long long top = (1ll << 10) - 1;
   const unsigned cx = (unsigned)min(top, max(0ll, dx >> (shx - kSubBits))) & ((1u << kSubBits) - 1);
   const unsigned cy = (unsigned)min(top, max(0ll, dy >> (shy - kSubBits))) & ((1u << kSubBits) - 1);
   return spread6(cx) | (spread6(cy) << 1);
 }
 
+template <int kBB>
 __global__ __launch_bounds__(kRefThreads) void bin_refine_kernel(int2* __restrict__ sorted, int* __restrict__ perm,
                                                                  const long long chunk,
                                                                  const unsigned* __restrict__ cursor,
                                                                  const unsigned* __restrict__ pstart, const int4 rb,
                                                                  const int shx, const int shy) {
+  constexpr int kNB = Bins<kBB>::kN, kSubs = Bins<kBB>::kSubs, kRefPer = Bins<kBB>::kRefPer;
+  constexpr int kRefPts = kRefThreads * kRefPer;
   __shared__ int2 sx[kRefPts];
   __shared__ int sp[kRefPts];
   __shared__ unsigned h[kSubs];
   __shared__ unsigned wsum[kRefThreads / kWave];
   __shared__ int the_bin;
-  static_assert(kSubs == kRefThreads, "one sub-cell count per thread");
+  static_assert(kSubs % kRefThreads == 0, "whole sub-cell counts per thread");
+  constexpr int kQ = kSubs / kRefThreads;
   sorted += (long long)blockIdx.y * chunk;  // block (piece, chunk)
   perm += (long long)blockIdx.y * chunk;
   cursor += (size_t)blockIdx.y * kBins;
   pstart += (size_t)blockIdx.y * kPStride;
   const unsigned piece = blockIdx.x;
-  if (piece >= pstart[kBins]) return;
+  if (piece >= pstart[kNB]) return;
   if (threadIdx.x == 0) {  // the last bin whose first piece is <= piece
-    int lo = 0, hi = kBins - 1;
+    int lo = 0, hi = kNB - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (pstart[mid] <= piece) lo = mid; else hi = mid - 1;
     }
     the_bin = lo;
   }
-  h[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kSubs; i += kRefThreads) h[i] = 0;
   __syncthreads();
   const int b = the_bin;
   const unsigned start = b ? cursor[b - 1] : 0u, end = cursor[b];
@@ -889,12 +908,22 @@ __global__ __launch_bounds__(kRefThreads) void bin_refine_kernel(int2* __restric
   }
 #pragma unroll
   for (int k = 0; k < kRefPer; ++k) {
-    key[k] = threadIdx.x + k * kRefThreads < cnt ? sub_of(p[k], rb, shx, shy) : (unsigned)kSubs;
+    key[k] = threadIdx.x + k * kRefThreads < cnt ? sub_of<kBB>(p[k], rb, shx, shy) : (unsigned)kSubs;
     r[k] = key[k] < (unsigned)kSubs ? atomicAdd(&h[key[k]], 1u) : 0u;
   }
   __syncthreads();
-  const unsigned first = block_exclusive_scan<kRefThreads>(h[threadIdx.x], wsum);
-  h[threadIdx.x] = first;  // each thread rewrites only its own sub-cell
+  unsigned v[kQ], mine = 0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    v[q] = h[threadIdx.x * kQ + q];
+    mine += v[q];
+  }
+  unsigned run = block_exclusive_scan<kRefThreads>(mine, wsum);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {  // each thread rewrites only its own sub-cells
+    h[threadIdx.x * kQ + q] = run;
+    run += v[q];
+  }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kRefPer; ++k)
@@ -1139,6 +1168,29 @@ static void launch_sorted(const KIndex& ix, const int2* p, const int* perm, long
   hipLaunchKernelGGL(map_sorted_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, p, perm, n, out);
 }
 
+// One round of sort passes over the nc chunks of m points at p: count, scan,
+// scatter and (when the root box is at least 1024 units a side) refine.
+template <int kBB>
+static void sort_passes(const int4 rb, const int2* p, const long long m, const long long chunk, const unsigned nc,
+                        unsigned* tot, unsigned* cursor, unsigned* pstart, int2* sorted, int* perm,
+                        hipStream_t stream) {
+  constexpr int kSubBits = Bins<kBB>::kSubBits;
+  constexpr long long kRefPts = (long long)kRefThreads * Bins<kBB>::kRefPer;
+  int shx = 0, shy = 0;
+  while (((1ll << kBB) << shx) < (long long)rb.y - rb.x) ++shx;
+  while (((1ll << kBB) << shy) < (long long)rb.w - rb.z) ++shy;
+  const bool refine = shx >= kSubBits && shy >= kSubBits;
+  hipLaunchKernelGGL(bin_count_kernel<kBB>, dim3((unsigned)((chunk + kBinBlockPts - 1) / kBinBlockPts), nc),
+                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, shx, shy, tot);
+  hipLaunchKernelGGL(bin_scan_kernel<kBB>, dim3(nc), dim3(kBinThreads), 0, stream, tot, cursor,
+                     refine ? pstart : nullptr);
+  hipLaunchKernelGGL(bin_scatter_kernel<kBB>, dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc),
+                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, shx, shy, cursor, sorted, perm);
+  if (refine)  // at most chunk / kRefPts + bins pieces per chunk
+    hipLaunchKernelGGL(bin_refine_kernel<kBB>, dim3((unsigned)(chunk / kRefPts + Bins<kBB>::kN), nc),
+                       dim3(kRefThreads), 0, stream, sorted, perm, chunk, cursor, pstart, rb, shx, shy);
+}
+
 hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
                       const Tuning& t, int num_cu, hipStream_t stream, LaunchTimer* timer) {
   const int2* p = reinterpret_cast<const int2*>(xy);
@@ -1177,26 +1229,16 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
   unsigned* pstart = cursor + max_nc * kBins;
   int2* sorted = reinterpret_cast<int2*>(static_cast<char*>(scratch) + hist_bytes);
   int* perm = reinterpret_cast<int*>(sorted + super);
-  const int4 rb = ix.root_box;
-  int shx = 0, shy = 0;
-  while (((1ll << kBinBits) << shx) < (long long)rb.y - rb.x) ++shx;
-  while (((1ll << kBinBits) << shy) < (long long)rb.w - rb.z) ++shy;
-  const bool refine = shx >= kSubBits && shy >= kSubBits;
   hipLaunchKernelGGL(bin_zero_kernel, dim3((unsigned)std::min<long long>(max_nc * 4, 1024)), dim3(1024), 0, stream,
                      tot, max_nc * kBins);
   for (long long s0 = 0; s0 < n && e == hipSuccess; s0 += super) {
     const long long m = std::min(super, (long long)n - s0);  // the first super-chunk is the largest
     const unsigned nc = (unsigned)((m + chunk - 1) / chunk);
     mark(2);
-    hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((chunk + kBinBlockPts - 1) / kBinBlockPts), nc),
-                       dim3(kBinThreads), 0, stream, p + s0, m, chunk, rb, shx, shy, tot);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(nc), dim3(kBinThreads), 0, stream, tot, cursor,
-                       refine ? pstart : nullptr);
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc),
-                       dim3(kBinThreads), 0, stream, p + s0, m, chunk, rb, shx, shy, cursor, sorted, perm);
-    if (refine)  // at most chunk / kRefPts + kBins pieces per chunk
-      hipLaunchKernelGGL(bin_refine_kernel, dim3((unsigned)(chunk / kRefPts + kBins), nc), dim3(kRefThreads), 0,
-                         stream, sorted, perm, chunk, cursor, pstart, rb, shx, shy);
+    if (ix.presort_bin_bits == 6)
+      sort_passes<6>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, perm, stream);
+    else
+      sort_passes<5>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, perm, stream);
     for (unsigned c = 0; c < nc; ++c) {
       const long long c0 = (long long)c * chunk, mc = std::min(chunk, m - c0);
       mark(0);
@@ -1271,7 +1313,7 @@ hipError_t launch_count(const int32_t* ids, int64_t n, int32_t nb, unsigned long
     hipLaunchKernelGGL(bin_zero_kernel, dim3(4), dim3(1024), 0, stream, tot, (long long)kBins);
     hipLaunchKernelGGL(cnt_bucket_count_kernel, dim3(nblk), dim3(kBinThreads), 0, stream,
                        reinterpret_cast<const int*>(ids), (long long)n, nb, tot, counts);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(kBinThreads), 0, stream, tot, cursor, nullptr);
+    hipLaunchKernelGGL(bin_scan_kernel<6>, dim3(1), dim3(kBinThreads), 0, stream, tot, cursor, nullptr);
     hipLaunchKernelGGL(cnt_bucket_scatter_kernel, dim3(nblk), dim3(kBinThreads), 0, stream,
                        reinterpret_cast<const int*>(ids), (long long)n, nb, cursor, sorted);
     hipLaunchKernelGGL(cnt_slice_kernel, dim3((unsigned)nbk, (unsigned)ns), dim3(1024), 0, stream, sorted, cursor, nb,
