@@ -776,7 +776,7 @@ __global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ t
 // runs, so a wave's stores touch a few cache lines rather than one per lane:
 // sorted[pos] = point, perm[pos] = its index in the chunk. (The order inside
 // a bin varies from run to run; no output depends on it.)
-constexpr int kScatPer = 8;
+constexpr int kScatPer = 12;
 constexpr long long kScatPts = (long long)kBinThreads * kScatPer;
 
 template <int kBB>

@@ -128,6 +128,30 @@ def test_spatial_presort_never_changes_results(torch_cuda, bm, grid221k):
     assert (a.cpu().numpy()[sub] == H.map(pts[sub])).all()
 
 
+@pytest.mark.parametrize("side", [40, 3000])
+def test_spatial_presort_small_root_box(torch_cuda, bm, side):
+    """Pre-sorted calls over indexes whose root box is narrower than the
+    1024 x 1024 sort grid (side 40: bins only, no refinement; side 3000: both),
+    with points outside the box too: the same ids as unsorted, and as brute
+    force on a sample."""
+    torch = torch_cuda
+    rng = np.random.default_rng(side)
+    k = 30
+    rings = [[(0, 0), (side * (j + 1) // k, 0), (side * (j + 1) // k, side * (j + 1) // k), (0, side * (j + 1) // k)]
+             for j in range(k)]
+    off, verts, ix = _rings_index(bm, rings)
+    n = (1 << 20) + 321
+    pts = rng.integers(-3, side + 4, size=(n, 2)).astype(np.int32)
+    xy = torch.from_numpy(pts).cuda()
+    say("presort small root box", side, n)
+    a = bm.map_points(ix, xy, tuning=bm.Tuning(4, 8, 2048, 1))
+    b = bm.map_points(ix, xy, tuning=bm.Tuning(4, 8, 2048, 0))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    sub = rng.choice(n, 20_000, replace=False)
+    assert (a.cpu().numpy()[sub] == oracle.brute(off, verts, pts[sub])).all()
+
+
 def test_grid221k_full_size_sampled_and_partition_property(torch_cuda, bm, grid221k):
     """100M points in the benchmark's launch shape: sampled outputs against the
     oracle, and at every point the partition property (an id exactly when the
