@@ -1,11 +1,13 @@
 // Point -> block mapping kernels for gfx950 (wave64).
 //
 // One kernel does the whole path for a tile of 64 points per wavefront:
-//   1. hierarchical box filter (paper Sec. III): every point is tested
-//      against the level-0 boxes (staged in LDS, same box for all lanes),
-//      then against the children of each surviving group, level by level.
-//      Survivors of each level are compacted into a per-wave LDS list of
-//      (node, point) items with a wavefront ballot + mbcnt prefix count.
+//   1. hierarchical box filter (paper Sec. III): the root's slot table gives
+//      each point its candidate level-0 groups, whose boxes are tested
+//      exactly; the children of every surviving group are then tested the
+//      same way. Survivors are compacted with a wavefront ballot + mbcnt
+//      prefix count into a per-wave LDS ring of (group, point) items, which
+//      is consumed 64 items per round whatever their level, or, for blocks,
+//      into a list of (block, point) pairs.
 //   2. crossing-number test (paper Sec. III-A) on every surviving
 //      (block, point) pair, edge-parallel: each pair's ring is cut into
 //      chunks of a few edges, the chunks of all pairs of the tile are dealt
@@ -45,7 +47,8 @@ struct WaveLds {
   unsigned best[kTile];
   unsigned par[kWave];     // crossing parity of the pairs of one round
   uint4 pair[kWave];       // per pair of a round: first listed edge, edges, first chunk, point slot
-  unsigned item[2][kCap];  // (node << kSlotBits | point slot) lists of the current and the next level
+  unsigned item[2][kCap];  // (node << kSlotBits | point slot) lists: the ring of group items and the pairs
+                           // (the cover form keeps its pairs in the first)
   unsigned char ovf[kTile];
   unsigned char ch_q[kCapChunk];  // pair (within the round) of each chunk of a window
 };
