@@ -180,6 +180,7 @@ def main():
     res["count_per_block"] = bench_count(bm, torch, out, g.n_blocks, args.steps)
     del xy, out
     torch.cuda.empty_cache()
+    res["quantize"] = bench_quantize(bm, torch, n, args.steps)
     if not args.no_batched:
         res["batched"] = bench_batched(bm, torch, g, ix)
     if args.quadtree8m or not args.no_served:
@@ -250,6 +251,37 @@ def bench_count(bm, torch, ids, n_blocks, steps):
     ms = e0.elapsed_time(e1) / steps
     log("count per block: %.3f ms per 100M ids (%.3g ids/s), equal to bincount: %s" % (ms, ids.shape[0] / ms * 1e3, ok))
     return {"ms": ms, "ids_per_s": ids.shape[0] / ms * 1e3, "equal_to_bincount": ok}
+
+
+def bench_quantize(bm, torch, n, steps):
+    """The quantiser on n resident (lon, lat) doubles, uniform over the globe:
+    16 bytes read and 8 written per point, against the HBM peak; checked
+    against torch's round-half-even of v * 2^22, plus 2^30."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    ll = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    ll[:, 0].uniform_(-180.0, 180.0, generator=gen)
+    ll[:, 1].uniform_(-90.0, 90.0, generator=gen)
+    q = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+    bm.quantize_lonlat(ll, q, s)
+    want = (torch.round(ll * 4194304.0).to(torch.int64) + (1 << 30)).to(torch.int32)
+    ok = bool(torch.equal(q, want))
+    del want
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        bm.quantize_lonlat(ll, q, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = 24.0 * n / (ms * 1e-3) / 1e9
+    log("quantize: %.3f ms per %d points (%.3g points/s, %.0f GB/s = %.1f%% of HBM peak), exact: %s" %
+        (ms, n, n / ms * 1e3, gbs, 100 * gbs / PEAK_HBM_GBS, ok))
+    del ll, q
+    torch.cuda.empty_cache()
+    return {"points": n, "ms": ms, "points_per_s": n / ms * 1e3, "achieved_GBs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS, "bytes_per_point": 24, "exact": ok}
 
 
 def bench_batched(bm, torch, g, ix, nb=10_000):
