@@ -164,9 +164,10 @@ typedef struct {
   int32_t blocks_per_cu;    /* workgroups per compute unit (1..8), capped at what fits */
   int32_t tile_points;      /* batched form: points per unit of work (multiple of 64, <= 2^20) */
   int32_t presort;          /* 1: a call of at least 2^20 points is first sorted along a Z-curve
-                               (a 64 x 64 Morton grid over the index, refined by 16 x 16
-                               sub-cells) in chunks of 2^22 points (2^26 for an index over
-                               256 MB), so that nearby points are mapped together; it uses
+                               (Morton bins over the index, refined by Morton sub-cells: a
+                               1024 x 1024 grid, or 4096 x 4096 for an index over 256 MB) in
+                               chunks of 2^22 points (2^26 for an index over 256 MB), so that
+                               nearby points are mapped together; it uses
                                12 bytes of stream-ordered device scratch (hipMallocAsync) per
                                point, for at most 2^27 points at a time (1.6 GB). 0: off */
 } bm_tuning;
