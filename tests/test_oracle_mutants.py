@@ -37,6 +37,9 @@ MUTANTS = [
     ("largest_id_wins",
      "if (best < 0 || b < best) best = (int32_t)b;",
      "if (best < 0 || b > best) best = (int32_t)b;"),
+    ("last_hit_wins_in_brute_force",
+     "        if (best < 0) best = (int32_t)b;",
+     "        best = (int32_t)b;"),
 ]
 
 
@@ -49,6 +52,7 @@ def _pin_calls():
               ("box conservative", pins.test_box_is_conservative, ()),
               ("unjittered grid", pins.test_unjittered_grid_closed_form, ()),
               ("partition grid1k", pins.test_partition_invariant, ("grid1k",)),
+              ("overlapping rectangles", pins.test_overlapping_rectangles_smallest_id, ()),
               ("hierarchy == brute grid1k", pins.test_hier_equals_brute_grid1k, ())]
     return calls
 

@@ -240,6 +240,33 @@ def test_partition_invariant(workload):
     assert ((out >= 0) == inside).all()
 
 
+def test_overlapping_rectangles_smallest_id():
+    """Overlapping axis-aligned rectangles (not a partition): containment has a
+    closed form (the half-open box), so the answer at every point is the
+    smallest id among the rectangles whose box holds it, or -1. Both routes,
+    with and without box rejection, under a random grouping."""
+    rng = np.random.default_rng(21)
+    m = 200
+    x0 = rng.integers(0, 900, m)
+    y0 = rng.integers(0, 900, m)
+    x1 = x0 + rng.integers(1, 300, m)
+    y1 = y0 + rng.integers(1, 300, m)
+    rings = [np.array([[a, c], [b, c], [b, d], [a, d]], np.int32) for a, b, c, d in zip(x0, x1, y0, y1)]
+    off = np.concatenate([[0], np.cumsum([4] * m)]).astype(np.int64)
+    verts = np.concatenate(rings)
+    pts = np.concatenate([rng.integers(-5, 1250, (20_000, 2)),
+                          np.stack([x0, y0], 1), np.stack([x1 - 1, y1 - 1], 1), np.stack([x1, y0], 1)]).astype(np.int32)
+    px, py = pts[:, :1].astype(np.int64), pts[:, 1:].astype(np.int64)
+    hit = (x0 <= px) & (px < x1) & (y0 <= py) & (py < y1)
+    want = np.where(hit.any(1), hit.argmax(1), -1)
+    assert (oracle.brute(off, verts, pts) == want).all()
+    assert (oracle.brute(off, verts, pts, box_reject=True) == want).all()
+    ids, hits = oracle.brute(off, verts, pts, count_hits=True)  # scans every block
+    assert (ids == want).all() and (hits == hit.sum(1)).all()
+    g = rng.integers(0, 7, m).astype(np.int32)
+    assert (oracle.Hier(off, verts, [7], [g]).map(pts) == want).all()
+
+
 def test_hier_equals_brute_grid1k():
     g = synth.geometry("grid1k")
     pts = synth.points("grid1k")
