@@ -128,6 +128,35 @@ def test_spatial_presort_never_changes_results(torch_cuda, bm, grid221k):
     assert (a.cpu().numpy()[sub] == H.map(pts[sub])).all()
 
 
+@pytest.mark.parametrize("kind", ["one_point_inside", "one_point_outside", "vertical_line", "two_clusters"])
+def test_spatial_presort_degenerate_distributions(torch_cuda, bm, kind):
+    """Pre-sorted calls whose points all fall in one bin (a single bin cut
+    into many refinement pieces), on one line, or in two tight clusters: the
+    same ids as unsorted, and as brute force on a sample."""
+    torch = torch_cuda
+    g = synth.geometry("grid1k")
+    ix = bm.Index.from_geometry(g)
+    n = (1 << 21) + 77
+    rng = np.random.default_rng(len(kind))
+    if kind == "one_point_inside":
+        pts = np.tile(np.array([[g.W // 3, g.W // 5]], np.int32), (n, 1))
+    elif kind == "one_point_outside":
+        pts = np.tile(np.array([[g.W + 10, -3]], np.int32), (n, 1))
+    elif kind == "vertical_line":
+        pts = np.stack([np.full(n, g.W // 2), rng.integers(-5, g.W + 5, n)], 1).astype(np.int32)
+    else:
+        c = rng.integers(0, 2, n)
+        pts = (np.array([[g.W // 7, g.W // 9], [g.W - 11, g.W - 13]])[c] + rng.integers(-2, 3, (n, 2))).astype(np.int32)
+    xy = torch.from_numpy(pts).cuda()
+    say("presort degenerate", kind, n)
+    a = bm.map_points(ix, xy, tuning=bm.Tuning(4, 8, 2048, 1))
+    b = bm.map_points(ix, xy, tuning=bm.Tuning(4, 8, 2048, 0))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    sub = rng.choice(n, 5_000, replace=False)
+    assert (a.cpu().numpy()[sub] == oracle.brute(g.vert_off, g.verts, pts[sub])).all()
+
+
 @pytest.mark.parametrize("side", [40, 3000])
 def test_spatial_presort_small_root_box(torch_cuda, bm, side):
     """Pre-sorted calls over indexes whose root box is narrower than the
