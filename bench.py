@@ -149,7 +149,7 @@ def main():
     log("dominant kernel: %d launches/step, %.3f ms each (%.0f points), sort phases %.3f ms/step; "
         "%.2f T algorithmic ops/s" % (launches, kernel_ms, pts_per_launch, tm["sort_ms"] / reps, achieved))
     res = {
-        "metric": "points mapped/sec on 1 GPU (plain kernel; batched and served forms reported beside it)",
+        "metric": "points mapped/sec on 1 GPU, served/batched vs plain kernel; p50/p99 latency",
         "value": value,
         "unit": "points/s",
         "n_gpus": 1,
@@ -175,6 +175,7 @@ def main():
         "hbm": {"achieved_GBs": hbm_gbs, "peak_GBs": PEAK_HBM_GBS, "frac": hbm_gbs / PEAK_HBM_GBS,
                 "bytes_per_point": BYTES_PER_POINT},
     }
+    res["all_levels_kept"] = bench_all_levels(bm, torch, g, xy, out, args.steps)
     if not args.no_cover:
         res["cover"] = bench_cover(bm, torch, g, ix, xy, out, args.steps)
     res["count_per_block"] = bench_count(bm, torch, out, g.n_blocks, args.steps)
@@ -195,6 +196,35 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(g, pts)
     print(json.dumps(res), flush=True)
+
+
+def bench_all_levels(bm, torch, g, xy, ref, steps):
+    """The same plain mapping with every level of the hierarchy kept
+    (regions, counties, tracts, blocks): the thin tract level, which the
+    default index leaves out, costs each point one more round of group
+    items. `ref` holds the default index's output for the same points."""
+    ix4 = bm.Index.from_geometry(g, keep_all_levels=True)
+    out = torch.empty_like(ref)
+    s = torch.cuda.current_stream()
+    bm.map_points(ix4, xy, out, s)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out, ref))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        bm.map_points(ix4, xy, out, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    n = xy.shape[0]
+    r = {"group_levels": ix4.info()["n_levels"], "points_per_s": n / wall, "ms_per_step": wall * 1e3,
+         "events_ms": e0.elapsed_time(e1) / steps, "same_ids_as_default_index": same}
+    log("every level kept (%d group levels): %.3f ms/step, %.3g points/s, same ids: %s" %
+        (r["group_levels"], wall * 1e3, n / wall, same))
+    ix4.close()
+    del out
+    return r
 
 
 def bench_cover(bm, torch, g, ix, xy, ref, steps):

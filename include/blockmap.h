@@ -78,6 +78,10 @@ typedef struct bm_index bm_index;
  *                 whose groups hold fewer than 4 entities on average is left
  *                 out of the index (the level above adopts its entities)
  *                 unless a group would then hold more than 256.
+ *   keep_all_levels  nonzero: keep every level given, thin ones included
+ *                 (each point then passes every level of the hierarchy;
+ *                 results are the same either way). Zero-initialise it when
+ *                 unused.
  *
  * The descriptor and its arrays are only read during bm_index_create. */
 typedef struct {
@@ -87,6 +91,7 @@ typedef struct {
   int32_t n_levels;
   const int64_t* n_groups;
   const int32_t* const* parent;
+  int32_t keep_all_levels;
 } bm_index_desc;
 
 /* Validate the descriptor, derive the half-open boxes of every block and

@@ -36,7 +36,8 @@ lib = C.CDLL(LIB_PATH)
 
 class IndexDesc(C.Structure):
     _fields_ = [("n_blocks", C.c_int64), ("vert_off", C.c_void_p), ("verts_xy", C.c_void_p),
-                ("n_levels", C.c_int32), ("n_groups", C.c_void_p), ("parent", C.c_void_p)]
+                ("n_levels", C.c_int32), ("n_groups", C.c_void_p), ("parent", C.c_void_p),
+                ("keep_all_levels", C.c_int32)]
 
 
 class IndexInfo(C.Structure):
@@ -180,20 +181,20 @@ def tuning_default() -> Tuning:
     return t
 
 
-def _desc(vert_off, verts, n_groups, parents):
+def _desc(vert_off, verts, n_groups, parents, keep_all_levels=False):
     vo = np.ascontiguousarray(vert_off, np.int64)
     vv = np.ascontiguousarray(verts, np.int32)
     ng = np.ascontiguousarray(n_groups, np.int64)
     pars = [np.ascontiguousarray(p, np.int32) for p in parents]
     parr = (C.c_void_p * max(len(pars), 1))(*[p.ctypes.data for p in pars])
     d = IndexDesc(vo.shape[0] - 1, vo.ctypes.data, vv.ctypes.data, len(pars),
-                  ng.ctypes.data if len(pars) else None, C.cast(parr, C.c_void_p))
+                  ng.ctypes.data if len(pars) else None, C.cast(parr, C.c_void_p), int(bool(keep_all_levels)))
     return d, (vo, vv, ng, pars, parr)
 
 
-def build_index_file(path: str, vert_off, verts, n_groups=(), parents=()) -> None:
+def build_index_file(path: str, vert_off, verts, n_groups=(), parents=(), *, keep_all_levels=False) -> None:
     """Build an index on the host only and write it to a file (no GPU needed)."""
-    d, keep = _desc(vert_off, verts, n_groups, parents)
+    d, keep = _desc(vert_off, verts, n_groups, parents, keep_all_levels)
     _check(lib.bm_index_build_file(C.byref(d), os.fsencode(path)))
     del keep
 
@@ -201,20 +202,20 @@ def build_index_file(path: str, vert_off, verts, n_groups=(), parents=()) -> Non
 class Index:
     """A block partition and its hierarchy, resident in device memory."""
 
-    def __init__(self, vert_off, verts, n_groups=(), parents=(), *, _handle=None):
+    def __init__(self, vert_off, verts, n_groups=(), parents=(), *, keep_all_levels=False, _handle=None):
         self._h = None
         if _handle is not None:
             self._h = _handle
             return
-        d, keep = _desc(vert_off, verts, n_groups, parents)
+        d, keep = _desc(vert_off, verts, n_groups, parents, keep_all_levels)
         h = C.c_void_p()
         _check(lib.bm_index_create(C.byref(d), C.byref(h)))
         del keep
         self._h = h
 
     @classmethod
-    def from_geometry(cls, g) -> "Index":
-        return cls(g.vert_off, g.verts, g.n_groups, g.parents)
+    def from_geometry(cls, g, *, keep_all_levels=False) -> "Index":
+        return cls(g.vert_off, g.verts, g.n_groups, g.parents, keep_all_levels=keep_all_levels)
 
     @classmethod
     def load(cls, path: str) -> "Index":

@@ -190,11 +190,12 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   // the candidates stay a superset of the true hits and no result changes. A
   // level stays if leaving it out would give a group more children than a
   // slot table holds. (220,900-block grid with tracts of ~3 blocks: mapping
-  // kernel 5.03 -> 4.70 ms per 100M points.)
+  // kernel 5.03 -> 4.70 ms per 100M points.) A caller may ask to keep every
+  // level.
   std::vector<const int32_t*> par(d->parent, d->parent + L);
   std::vector<std::vector<int32_t>> composed;
   composed.reserve(L);
-  for (int l = L - 1; l >= 0; --l) {
+  for (int l = d->keep_all_levels ? -1 : L - 1; l >= 0; --l) {
     const int64_t G = size[l], E = size[l + 1];
     if (E >= kThinFanout * G) continue;
     if (l == 0) {

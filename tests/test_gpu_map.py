@@ -111,6 +111,27 @@ def test_grid221k_two_million_vs_hierarchy_oracle(torch_cuda, bm, grid221k):
     assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all()
 
 
+def test_grid221k_every_level_kept(torch_cuda, bm, grid221k):
+    """The full four-level filter (regions, counties, tracts, blocks; the thin
+    tract level kept): the same ids as the oracle on 2M points plus boundary
+    points, and the same as the default index on a pre-sorted call of 5M."""
+    torch = torch_cuda
+    g, ix, H = grid221k
+    ix4 = bm.Index.from_geometry(g, keep_all_levels=True)
+    assert ix4.info()["n_levels"] == 3 and ix.info()["n_levels"] == 2
+    say("grid221k, every level kept: 2M points vs hierarchy oracle")
+    pts = np.concatenate([synth.points("grid221k", 2_000_000, i0=9_000_000), boundary_points(g, 20_000, seed=4)])
+    got = gpu_map(bm, torch, ix4, pts)
+    assert (got == H.map(pts)).all()
+    say("grid221k, every level kept: 5M pre-sorted points vs the default index")
+    xy = torch.from_numpy(synth.points("grid221k", 5_000_000, i0=20_000_000)).cuda()
+    a = bm.map_points(ix4, xy)
+    b = bm.map_points(ix, xy)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    ix4.close()
+
+
 def test_spatial_presort_never_changes_results(torch_cuda, bm, grid221k):
     """Calls above the pre-sort threshold, sorted or not, several chunks with
     a ragged tail: identical outputs, equal to the oracle on a sample."""

@@ -112,6 +112,39 @@ def test_thin_levels(tmp_path, top, kept):
         assert np.all(child[:, 2] >= 0)  # 256 children: still a slot table
 
 
+def test_keep_all_levels(tmp_path):
+    """keep_all_levels keeps a thin level: the 220,900-block grid's tracts
+    (~3 blocks each) stay as a level of their own between counties and blocks,
+    and every group's children are the entities the caller assigned to it."""
+    import paper_2005_03156_amd as bm
+    g = synth.geometry("grid221k")
+    p = str(tmp_path / "k.bmi")
+    bm.build_index_file(p, g.vert_off, g.verts, g.n_groups, g.parents, keep_all_levels=True)
+    ix = read_index(p)
+    sizes = [int(s) for s in g.n_groups]
+    assert ix["n_levels"] == len(sizes) == 3
+    assert ix["g0"] == sizes[0] and ix["leaf_base"] == sum(sizes)
+    # the tracts: node ids [s0 + s1, s0 + s1 + s2), their children are blocks
+    t0 = sizes[0] + sizes[1]
+    tr = ix["child"][t0:t0 + sizes[2]]
+    assert tr[:, 0].min() >= ix["leaf_base"] and tr[:, 1].max() == ix["leaf_base"] + g.n_blocks
+    assert int((tr[:, 1] - tr[:, 0]).sum()) == g.n_blocks
+    # the blocks under one tract are the ones whose parent is that tract
+    lid = ix["leaf"]["leaf_id"]
+    node_of_tract = {}
+    for k in range(0, sizes[2], 997):
+        blocks = lid[tr[k, 0] - ix["leaf_base"]:tr[k, 1] - ix["leaf_base"]]
+        parents = set(int(t) for t in g.parents[2][blocks])
+        assert len(parents) <= 1
+        if parents:
+            node_of_tract[parents.pop()] = k
+    assert len(node_of_tract) > 50
+    # the default build leaves the tracts out
+    p2 = str(tmp_path / "d.bmi")
+    bm.build_index_file(p2, g.vert_off, g.verts, g.n_groups, g.parents)
+    assert read_index(p2)["n_levels"] == 2
+
+
 def _table_candidates(ix, crec, gbox, px, py):
     """Candidate set of a point from a group's slot table, as one Python int
     (bit k = child k): x-rows then y-rows of W words each."""
