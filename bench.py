@@ -33,8 +33,9 @@ PEAK_HBM_GBS = 8000.0
 # 5 per box test (4 compares + and), 7 per edge test (2 compares, straddle,
 # x-range, parity), 12 per cross product -> 949.7 integer lane-ops per point.
 OPS_PER_POINT = 5 * 140.38 + 7 * 34.98 + 12 * 0.239
-# Algorithmic HBM bytes per point: 8 in + 4 out (the 51 MB index is read once
-# per launch from cache; 0.5 B/pt).
+# Algorithmic HBM bytes per point: 8 in + 4 out. The 158 MB index is left
+# out: it fits the 256 MB last-level cache, and read once per 100M-point step
+# it would add 1.6 B/pt.
 BYTES_PER_POINT = 12.0
 
 
@@ -435,7 +436,8 @@ def bench_served(bm, torch, g, ix, nreq):
         return {"points_per_s": st["points_per_s"], "requests_per_s": st["completed"] / wall,
                 "p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
                 "mean_requests_per_batch": st["mean_requests_per_batch"], "batches": st["batches"],
-                "identical_to_alone": bool(same)}
+                "identical_to_alone": bool(same),
+                "hbm_frac": BYTES_PER_POINT * st["points_per_s"] / 1e9 / PEAK_HBM_GBS}
 
     base_cfg = bm.server_cfg(mem_budget_bytes=2 << 30, max_batch_points=1 << 24, max_slots=1, n_streams=1,
                              flags=bm.BM_SERVER_ONE_PER_BATCH)
@@ -522,7 +524,8 @@ def bench_quadtree8m(bm, torch, g, ix):
     res = {"blocks": g.n_blocks, "vertices": int(g.verts.shape[0]), "points": N,
            "kernel_points_per_s": CH / (kern_ms * 1e-3), "kernel_ms_per_chunk": kern_ms,
            "end_to_end_points_per_s": N / t_wall, "end_to_end_first_chunk_identical": same,
-           "index_device_bytes": info["device_bytes"]}
+           "index_device_bytes": info["device_bytes"],
+           "kernel_hbm_frac": BYTES_PER_POINT * CH / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
     log("quadtree8m: kernel %.3f ms per 2^26 chunk (%.3g pts/s); end-to-end with PCIe %.3g pts/s "
         "(first chunk identical to the resident run: %s)" %
         (kern_ms, res["kernel_points_per_s"], res["end_to_end_points_per_s"], same))
