@@ -556,7 +556,42 @@ def cpu_baseline(g, pts):
     return {"value": passes * pts.shape[0] / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
             "sample": "%d full passes over the workload's %d points (%.1f s), hierarchy route, C + OpenMP"
                       % (passes, pts.shape[0], dt),
-            "single_thread_points_per_s": single}
+            "single_thread_points_per_s": single, "host": host_cpus()}
+
+
+def host_cpus():
+    """The host's CPUs as the OS reports them: logical CPUs, those this
+    process may run on, and physical cores (distinct (package, core) pairs)."""
+    r = {"logical": os.cpu_count()}
+    try:
+        r["usable"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        pairs, phys, core = set(), None, None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "physical id":
+                    phys = v.strip()
+                elif k == "core id":
+                    core = v.strip()
+                elif not k and phys is not None and core is not None:
+                    pairs.add((phys, core))
+                    phys = core = None
+        if phys is not None and core is not None:
+            pairs.add((phys, core))
+        if pairs:
+            r["physical_cores"] = len(pairs)
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    r["model"] = line.partition(":")[2].strip()
+                    break
+    except OSError:
+        pass
+    return r
 
 
 if __name__ == "__main__":
