@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--served-requests", type=int, default=20_000)
     ap.add_argument("--quadtree8m", action="store_true",
                     help="also measure the 8M-block graded mesh streamed over 1B points (stderr)")
+    ap.add_argument("--quadtree8m-kernel", action="store_true",
+                    help="only map one resident 2^26-point chunk over the 8M-block mesh a few times and "
+                         "print its timing (a short run for the profiler)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the mapping path has no multi-GPU form here "
@@ -85,6 +88,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.quadtree8m_kernel:
+        profile_quadtree8m(bm, torch, args)
+        return
     t0 = time.time()
     g = synth.geometry("grid221k")
     n = synth.n_points("grid221k")
@@ -459,6 +465,46 @@ def bench_served(bm, torch, g, ix, nreq):
                 (k, v["points_per_s"], v["requests_per_s"], v["p50_us"], v["p99_us"], v["mean_requests_per_batch"],
                  v["identical_to_alone"]))
     return res
+
+
+def profile_quadtree8m(bm, torch, args):
+    """One resident 2^26-point chunk of the 1B-point stream over the 8M-block
+    mesh, mapped once to warm up and then `steps` times, each call timed per
+    launch with HIP events on its stream. Prints one JSON line."""
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    t0 = time.time()
+    g = synth.geometry("quadtree8m")
+    ix = bm.Index.from_geometry(g)
+    CH = synth.QUADTREE["chunk"]
+    xy = torch.from_numpy(synth.points("quadtree8m", CH, 0)).cuda()
+    out = torch.empty(CH, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+    log("quadtree8m: %d blocks, index %.2f GB, chunk of %d points ready in %.1fs" % (
+        g.n_blocks, ix.info()["device_bytes"] / 1e9, CH, time.time() - t0))
+    bm.map_points(ix, xy, out, s)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 5))
+    tm = {"map_ms": 0.0, "sort_ms": 0.0, "map_launches": 0, "sort_launches": 0}
+    for _ in range(steps):
+        r = bm.map_points_timed(ix, xy, out, s)
+        for k in tm:
+            tm[k] += r[k]
+    launches = max(1, tm["map_launches"] // steps)
+    kernel_ms = tm["map_ms"] / steps / launches
+    res = {"workload": "8M-block graded quadtree mesh, one resident 2^26-point chunk", "points": CH,
+           "calls": steps, "map_launches_per_call": launches, "map_kernel_ms": kernel_ms,
+           "sort_ms_per_call": tm["sort_ms"] / steps,
+           "points_per_s_per_call": CH / ((tm["map_ms"] + tm["sort_ms"]) / steps * 1e-3)}
+    log("quadtree8m chunk: %d mapping launch(es) of %.3f ms, sort %.3f ms per call" % (
+        launches, kernel_ms, res["sort_ms_per_call"]))
+    ix.close()
+    print(json.dumps(res), flush=True)
 
 
 def bench_quadtree8m(bm, torch, g, ix):
