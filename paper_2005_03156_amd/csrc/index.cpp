@@ -27,7 +27,7 @@ namespace {
 constexpr int kTableMinChildren = 2;    // below this a group's children are simply all tested
 constexpr int kTableMaxChildren = 256;  // above this too
 constexpr int kThinFanout = 4;          // group levels with fewer children per group are left out
-constexpr int kTableLogSlots = 5;       // slots per axis: 32
+constexpr int kTableLogSlots = 5;       // slots per axis: 32 (16 for up to 16 children, 8 for up to 8)
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 
@@ -39,9 +39,11 @@ inline void grow(int4& a, const int4& b) {
 }
 
 // Slot table of a group with 2..256 children: the group box is cut into S = 32
-// equal power-of-two slots per axis, and the row of slot s of an axis (W =
-// ceil(children / 64) words) holds a bit for every child whose box overlaps it
-// on that axis; x-rows first, then y-rows. For a point in the group box, (x-slot mask & y-slot mask) is a superset
+// equal power-of-two slots per axis (S = 16 for up to 16 children, S = 8 for up
+// to 8, where the table then fills one 128-byte line), and the row of slot s of
+// an axis (W = ceil(children / 64) words) holds a bit for every child whose box
+// overlaps it on that axis; x-rows first, then y-rows, starting on a 128-byte
+// boundary. For a point in the group box, (x-slot mask & y-slot mask) is a superset
 // of the children whose boxes contain it; the exact half-open box test is then
 // run on those children only, so the filter's result is unchanged.
 template <class BoxOf>
@@ -49,12 +51,12 @@ int4 make_table(BoxOf box_of, int c0, int c1, const int4& g, std::vector<uint64_
   int4 r = make_int4(c0, c1, -1, 0);
   const int m = c1 - c0;
   if (m < kTableMinChildren || m > kTableMaxChildren || g.x >= g.y || g.z >= g.w) return r;
-  const int logS = kTableLogSlots, S = 1 << logS, W = (m + 63) / 64;
+  const int logS = m <= 8 ? 3 : m <= 16 ? 4 : kTableLogSlots, S = 1 << logS, W = (m + 63) / 64;
   const int64_t wx = (int64_t)g.y - g.x, wy = (int64_t)g.w - g.z;
   int shx = 0, shy = 0;
   while (((int64_t)S << shx) < wx) ++shx;
   while (((int64_t)S << shy) < wy) ++shy;
-  const size_t off = masks.size();
+  const size_t off = (masks.size() + 15) & ~(size_t)15;
   if (off + 2 * (size_t)S * W > (size_t)INT32_MAX) return r;
   masks.resize(off + 2 * (size_t)S * W, 0);
   for (int c = c0; c < c1; ++c) {

@@ -215,6 +215,38 @@ def test_slot_tables_with_several_words_per_row(tmp_path, per_group):
     _check_tables(ix, [(child[k], ix["box"][k]) for k in np.flatnonzero(has)], rng, tries=300)
 
 
+def test_slot_tables_of_small_groups(tmp_path):
+    """Groups of up to 8 children get 8 slots per axis, up to 16 get 16, larger
+    ones 32; every table starts on a 128-byte boundary, tables do not overlap,
+    and each is a superset of the children containing a point. 1,024 blocks in
+    consecutive groups of 2..40."""
+    import paper_2005_03156_amd as bm
+    g = synth.geometry("grid1k")
+    sizes, left = [], g.n_blocks
+    rng = np.random.default_rng(11)
+    while left > 0:
+        k = min(left, int(rng.integers(2, 41)))
+        sizes.append(k)
+        left -= k
+    parent = np.repeat(np.arange(len(sizes)), sizes).astype(np.int32)
+    p = str(tmp_path / "s.bmi")
+    bm.build_index_file(p, g.vert_off, g.verts, [len(sizes)], [parent])
+    ix = read_index(p)
+    child = ix["child"][:len(sizes)]
+    m = child[:, 1] - child[:, 0]
+    has = child[:, 2] >= 0
+    assert np.array_equal(has, m >= 2)
+    logS = child[:, 3] & 0xFF
+    assert np.array_equal(logS[has], np.where(m[has] <= 8, 3, np.where(m[has] <= 16, 4, 5)))
+    assert {3, 4, 5} <= set(logS[has].tolist())
+    off = child[has, 2].astype(np.int64)
+    assert np.all(off % 16 == 0)
+    span = 2 * (1 << logS[has].astype(np.int64))  # words: one per row (W = 1)
+    order = np.argsort(off)
+    assert np.all(off[order][:-1] + span[order][:-1] <= off[order][1:])
+    _check_tables(ix, [(child[k], ix["box"][k]) for k in np.flatnonzero(has)], rng, tries=300)
+
+
 def test_y_slabs_list_every_straddling_edge(grid221k_index):
     """For any height in a leaf's y-extent, its slab lists (as vertex pairs)
     every edge of the caller's ring that straddles that height, and only
