@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-cover", action="store_true", help="skip the cell-cover (fast approach) leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--no-all-levels", action="store_true",
+                    help="skip the leg that keeps every hierarchy level (its launches would mix into a profile)")
     ap.add_argument("--served-requests", type=int, default=20_000)
     ap.add_argument("--quadtree8m", action="store_true",
                     help="also measure the 8M-block graded mesh streamed over 1B points (stderr)")
@@ -182,7 +184,8 @@ def main():
         "hbm": {"achieved_GBs": hbm_gbs, "peak_GBs": PEAK_HBM_GBS, "frac": hbm_gbs / PEAK_HBM_GBS,
                 "bytes_per_point": BYTES_PER_POINT},
     }
-    res["all_levels_kept"] = bench_all_levels(bm, torch, g, xy, out, args.steps)
+    if not args.no_all_levels:
+        res["all_levels_kept"] = bench_all_levels(bm, torch, g, xy, out, args.steps)
     if not args.no_cover:
         res["cover"] = bench_cover(bm, torch, g, ix, xy, out, args.steps)
     res["count_per_block"] = bench_count(bm, torch, out, g.n_blocks, args.steps)

@@ -248,6 +248,51 @@ __device__ __forceinline__ void emit_ring(WaveLds& S, bool pred, unsigned node, 
   tail = min(tail + k, lim);
 }
 
+// Two candidates per lane in one append (to the ring, or to list `dst` for
+// emit2): all lanes' first items, then their second items. The order of a
+// list does not change any result.
+__device__ __forceinline__ void emit2_ring(WaveLds& S, const bool p1, const unsigned n1, const bool p2,
+                                           const unsigned n2, const int plane, unsigned& tail, const unsigned lim) {
+  const unsigned long long m1 = __ballot(p1), m2 = __ballot(p2);
+  if ((m1 | m2) == 0ull) return;
+  const unsigned k1 = (unsigned)__popcll(m1), k = k1 + (unsigned)__popcll(m2);
+  const unsigned s1 = tail + lanes_below(m1), s2 = tail + k1 + lanes_below(m2);
+  const unsigned i1 = (n1 << kSlotBits) | (unsigned)plane, i2 = (n2 << kSlotBits) | (unsigned)plane;
+  if (tail + k <= lim) {  // wave-uniform: every new item fits
+    if (p1) S.item[0][s1 & (kCap - 1)] = i1;
+    if (p2) S.item[0][s2 & (kCap - 1)] = i2;
+  } else {
+    if (p1) {
+      if (s1 < lim) S.item[0][s1 & (kCap - 1)] = i1; else S.ovf[plane] = 1;
+    }
+    if (p2) {
+      if (s2 < lim) S.item[0][s2 & (kCap - 1)] = i2; else S.ovf[plane] = 1;
+    }
+  }
+  tail = min(tail + k, lim);
+}
+
+__device__ __forceinline__ void emit2(WaveLds& S, const int dst, const bool p1, const unsigned n1, const bool p2,
+                                      const unsigned n2, const int plane, unsigned& cnt) {
+  const unsigned long long m1 = __ballot(p1), m2 = __ballot(p2);
+  if ((m1 | m2) == 0ull) return;
+  const unsigned k1 = (unsigned)__popcll(m1), k = k1 + (unsigned)__popcll(m2);
+  const unsigned s1 = cnt + lanes_below(m1), s2 = cnt + k1 + lanes_below(m2);
+  const unsigned i1 = (n1 << kSlotBits) | (unsigned)plane, i2 = (n2 << kSlotBits) | (unsigned)plane;
+  if (cnt + k <= (unsigned)kCap) {  // wave-uniform: every new item fits
+    if (p1) S.item[dst][s1] = i1;
+    if (p2) S.item[dst][s2] = i2;
+  } else {
+    if (p1) {
+      if (s1 < (unsigned)kCap) S.item[dst][s1] = i1; else S.ovf[plane] = 1;
+    }
+    if (p2) {
+      if (s2 < (unsigned)kCap) S.item[dst][s2] = i2; else S.ovf[plane] = 1;
+    }
+  }
+  cnt += k;
+}
+
 // Children of one group per lane (ci = child record, gb = group box, pp =
 // the lane's point), in a round whose lanes may hold groups of different
 // levels: every child whose half-open box holds pp is emitted; children that
@@ -264,11 +309,14 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
   const unsigned sub = leaves ? (unsigned)ix.leaf_base : 0u;
   const int shift = leaves ? 6 : 5;
   const int m = has ? ci.y - ci.x : 0;
-  for (int base = 0; wave_any(base < m); base += 64) {
-    unsigned long long cand = 0ull;
+  // children in windows of 128 (two 64-bit candidate words, lo then hi), so
+  // that a lane's candidates of both words are taken in one loop
+  for (int base = 0; wave_any(base < m); base += 128) {
+    unsigned long long lo = 0ull, hi = 0ull;
     if (base < m) {
-      const int mm = min(64, m - base);
-      cand = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
+      const int mm = min(128, m - base);
+      lo = mm >= 64 ? ~0ull : ((1ull << mm) - 1ull);
+      hi = mm <= 64 ? 0ull : mm == 128 ? ~0ull : ((1ull << (mm - 64)) - 1ull);
       if (ci.z >= 0) {  // slot table: S x-rows then S y-rows of W words
         const int logS = ci.w & 0xff, shx = (ci.w >> 8) & 0xff, shy = (ci.w >> 16) & 0xff;
         const unsigned W = (unsigned)ci.w >> 24;
@@ -276,28 +324,53 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
         const unsigned sx = ((unsigned)pp.x - (unsigned)gb.x) >> shx;
         const unsigned sy = ((unsigned)pp.y - (unsigned)gb.z) >> shy;
         if (pp.x < gb.x || pp.y < gb.z || sx >= S_ || sy >= S_) {
-          cand = 0ull;
+          lo = hi = 0ull;
         } else {
           const unsigned w = (unsigned)base >> 6;
-          cand &= ix.slot_mask[(unsigned)ci.z + sx * W + w] & ix.slot_mask[(unsigned)ci.z + (S_ + sy) * W + w];
+          const unsigned long long* rx = ix.slot_mask + ((unsigned)ci.z + sx * W);
+          const unsigned long long* ry = ix.slot_mask + ((unsigned)ci.z + (S_ + sy) * W);
+          lo &= rx[w] & ry[w];
+          if (mm > 64) hi &= rx[w + 1] & ry[w + 1];
         }
       }
     }
     const unsigned c0 = (unsigned)(ci.x + base);
-    while (wave_any(cand != 0ull)) {
-      const bool h1 = cand != 0ull;
-      const unsigned n1 = h1 ? c0 + (unsigned)__builtin_ctzll(cand) : sub;
-      cand &= cand - 1ull;
-      const bool h2 = cand != 0ull;
-      const unsigned n2 = h2 ? c0 + (unsigned)__builtin_ctzll(cand) : sub;
-      cand &= cand - 1ull;
+    // two candidates per lane and step: box tests, then the appends
+    auto step = [&](const bool h1, const unsigned n1, const bool h2, const unsigned n2) {
       const int4 bx1 = *reinterpret_cast<const int4*>(rec + ((size_t)(n1 - sub) << shift));
       const int4 bx2 = *reinterpret_cast<const int4*>(rec + ((size_t)(n2 - sub) << shift));
       const bool in1 = h1 && in_box(bx1, pp), in2 = h2 && in_box(bx2, pp);
-      emit_ring(S, in1 && !leaves, n1, pl, tail, lim);
-      emit(S, 1, in1 && leaves, n1, pl, pcnt);
-      emit_ring(S, in2 && !leaves, n2, pl, tail, lim);
-      emit(S, 1, in2 && leaves, n2, pl, pcnt);
+      emit2_ring(S, in1 && !leaves, n1, in2 && !leaves, n2, pl, tail, lim);
+      emit2(S, 1, in1 && leaves, n1, in2 && leaves, n2, pl, pcnt);
+    };
+    if (!wave_any(hi != 0ull)) {  // every lane's candidates in the first word
+      while (wave_any(lo != 0ull)) {
+        const bool h1 = lo != 0ull;
+        const unsigned n1 = h1 ? c0 + (unsigned)__builtin_ctzll(lo) : sub;
+        lo &= lo - 1ull;
+        const bool h2 = lo != 0ull;
+        const unsigned n2 = h2 ? c0 + (unsigned)__builtin_ctzll(lo) : sub;
+        lo &= lo - 1ull;
+        step(h1, n1, h2, n2);
+      }
+    } else {
+      while (wave_any((lo | hi) != 0ull)) {
+        bool a = lo != 0ull;
+        unsigned long long v = a ? lo : hi;
+        const bool h1 = v != 0ull;
+        const unsigned n1 = h1 ? c0 + (a ? 0u : 64u) + (unsigned)__builtin_ctzll(v) : sub;
+        v &= v - 1ull;
+        lo = a ? v : lo;
+        hi = a ? hi : v;
+        a = lo != 0ull;
+        v = a ? lo : hi;
+        const bool h2 = v != 0ull;
+        const unsigned n2 = h2 ? c0 + (a ? 0u : 64u) + (unsigned)__builtin_ctzll(v) : sub;
+        v &= v - 1ull;
+        lo = a ? v : lo;
+        hi = a ? hi : v;
+        step(h1, n1, h2, n2);
+      }
     }
   }
 }
