@@ -66,7 +66,8 @@ typedef struct bm_index bm_index;
  *   verts_xy      interleaved (x, y) int32 vertices, each coordinate in
  *                 [0, 2^31 - 1]. A ring is closed implicitly from its last
  *                 vertex to its first; a stored closing copy of the first
- *                 vertex is harmless. Every ring has at least 3 vertices.
+ *                 vertex is harmless. Every ring has at least 3 and at most
+ *                 2^24 vertices.
  *                 Holes or several parts can be joined into one ring by a
  *                 bridge walked once each way (its crossings cancel).
  *   n_levels      number of group levels above the blocks (0 = no hierarchy).
@@ -99,7 +100,7 @@ typedef struct {
  * copy everything to the current HIP device. *out receives the handle, owned
  * by the caller until bm_index_destroy. Synchronous.
  * Errors: BM_EINVAL (null pointer, bad sizes or offsets, ring with fewer than
- * 3 vertices, parent out of range), BM_ERANGE (coordinate outside
+ * 3 or more than 2^24 vertices, parent out of range), BM_ERANGE (coordinate outside
  * [0, 2^31 - 1], more than 2^26 nodes, or slab edge lists of 2^31 or more
  * entries), BM_ENOMEM, BM_EHIP. */
 int bm_index_create(const bm_index_desc* desc, bm_index** out);

@@ -27,6 +27,8 @@ namespace {
 constexpr int kTableMinChildren = 2;    // below this a group's children are simply all tested
 constexpr int kTableMaxChildren = 256;  // above this too
 constexpr int kThinFanout = 4;          // group levels with fewer children per group are left out
+constexpr int64_t kMaxRingVerts = (int64_t)1 << 24;       // vertices per ring
+constexpr int64_t kMaxSlabEdges = 4 * kMaxRingVerts + 64;  // the longest slab list such a ring gives
 constexpr int kTableLogSlots = 5;       // slots per axis: 32 (16 for up to 16 children, 8 for up to 8)
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
@@ -166,8 +168,10 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
       const int64_t m = d->vert_off[b + 1] - d->vert_off[b];
       if (m < 3)
         return fail(BM_EINVAL, "bm_index_create: ring " + std::to_string(b) + " has fewer than 3 vertices");
-      if (m > (int64_t)1 << 28)
-        return fail(BM_EINVAL, "bm_index_create: ring " + std::to_string(b) + " has more than 2^28 vertices");
+      // A slab lists at most 4m + 64 edges, so the edge chunks that one
+      // crossing-test round of 64 pairs deals out stay below 2^31.
+      if (m > kMaxRingVerts)
+        return fail(BM_EINVAL, "bm_index_create: ring " + std::to_string(b) + " has more than 2^24 vertices");
     }
     const int64_t V = d->vert_off[B];
     for (int64_t k = 0; k < 2 * V; ++k)
@@ -455,7 +459,7 @@ bool consistent(const HostIndex& h) {
     }
     if (off[0] != 0) return false;
     for (int64_t j = 0; j < K; ++j)
-      if (off[j] > off[j + 1]) return false;
+      if (off[j] > off[j + 1] || off[j + 1] - off[j] > kMaxSlabEdges) return false;
     if (r.ent + off[K] > NE) return false;
   }
   return true;

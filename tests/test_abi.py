@@ -73,6 +73,10 @@ def test_descriptor_validation_without_gpu():
     d, keep = _square_desc(bm, [[0, 0], [10, 0]], [0, 2])
     rc, msg = _create(bm, d)
     assert rc == bm.BM_EINVAL and "fewer than 3" in msg
+    # ring above 2^24 vertices (the buffer is as long as declared)
+    d, keep = _square_desc(bm, np.zeros(((1 << 24) + 1, 2), np.int32), [0, (1 << 24) + 1])
+    rc, msg = _create(bm, d)
+    assert rc == bm.BM_EINVAL and "2^24" in msg
     # vert_off[0] != 0
     d, keep = _square_desc(bm, sq, [1, 4])
     rc, msg = _create(bm, d)

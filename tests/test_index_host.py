@@ -293,3 +293,52 @@ def test_build_file_rejects_bad_input(tmp_path):
     with pytest.raises(bm.BlockmapError) as e:
         bm.build_index_file(str(tmp_path / "x.bmi"), [0, 3], [[0, 0], [5, -2], [0, 5]])
     assert e.value.code == bm.BM_ERANGE
+
+
+def test_load_rejects_malformed_files(tmp_path):
+    """bm_index_load checks a file before anything reaches the device: a
+    truncated file, a wrong magic, a decreasing slab offset, an edge list
+    past the end, a child range past the nodes and a slot table of 2^7 slots
+    all give BM_EIO; the unmodified file passes the checks (on a machine
+    without a GPU it then fails only at the upload)."""
+    import ctypes as C
+    import paper_2005_03156_amd as bm
+    g = synth.geometry("grid1k")
+    good = str(tmp_path / "good.bmi")
+    bm.build_index_file(good, g.vert_off, g.verts, g.n_groups, g.parents)
+    buf = bytearray(open(good, "rb").read())
+    ix = read_index(good)
+    n_grp = len(ix["grp"])
+    grp_at = 64 + 8                     # after magic, scalars, n_verts and the count
+    leaf_at = grp_at + 32 * n_grp + 8   # first leaf record
+
+    def load(data):
+        path = str(tmp_path / "x.bmi")
+        open(path, "wb").write(bytes(data))
+        h = C.c_void_p()
+        rc = bm.lib.bm_index_load(path.encode(), C.byref(h))
+        if rc == bm.BM_OK:
+            bm.lib.bm_index_destroy(h)
+        return rc, bm.lib.bm_last_error().decode()
+
+    rc, _ = load(buf)
+    assert rc != bm.BM_EIO
+    cases = {}
+    cases["truncated"] = buf[:-5]
+    bad = bytearray(buf); bad[7:8] = b"9"; cases["magic"] = bad
+    # a leaf with inline offsets and at least two slabs: make them decrease
+    leaf = ix["leaf"]
+    k = next(i for i in range(len(leaf)) if not (int(leaf[i]["packed"]) & EXT) and (int(leaf[i]["packed"]) >> 8) & 0xFF >= 1)
+    bad = bytearray(buf); o = leaf_at + 64 * k + 32
+    bad[o + 1] = 200; bad[o + 2] = 100; cases["decreasing slab offsets"] = bad
+    bad = bytearray(buf); o = leaf_at + 64 * k + 16
+    bad[o:o + 8] = np.int64(len(ix["ent"]) + 1).tobytes(); cases["edge list past the end"] = bad
+    bad = bytearray(buf); o = grp_at + 32 * 0 + 16 + 4
+    bad[o:o + 4] = np.int32(len(ix["box"]) + 5).tobytes(); cases["child range past the nodes"] = bad
+    t = next(i for i in range(n_grp) if int(ix["child"][i][2]) >= 0)
+    bad = bytearray(buf); o = grp_at + 32 * t + 16 + 12
+    packed = int(ix["child"][t][3])
+    bad[o:o + 4] = np.int32((packed & ~0xFF) | 7).tobytes(); cases["slot table of 2^7 slots"] = bad
+    for name, data in cases.items():
+        rc, msg = load(data)
+        assert rc == bm.BM_EIO, (name, rc, msg)
