@@ -276,6 +276,48 @@ def test_heavy_ring_and_many_small(torch_cuda, bm):
     assert (got == oracle.brute(off, verts, pts)).all()
 
 
+def _comb(T=1500, H=10000, o=1000):
+    """A comb: a base [0, 20(T-1)+10) x [0, 100) with T teeth [20i, 20i+10) x
+    [100, H), shifted by (o, o). Every tooth edge straddles every height above
+    the base, so the ring's y-slabs list ~2T edges each."""
+    v = [(0, 0), (20 * (T - 1) + 10, 0)]
+    for i in range(T - 1, -1, -1):
+        v += [(20 * i + 10, H), (20 * i, H)]
+        if i > 0:
+            v += [(20 * i, 100), (20 * (i - 1) + 10, 100)]
+    return np.array(v, np.int32) + o
+
+
+def _comb_inside(pts, T=1500, H=10000, o=1000):
+    x, y = pts[:, 0].astype(np.int64) - o, pts[:, 1].astype(np.int64) - o
+    return (x >= 0) & (x < 20 * (T - 1) + 10) & (y >= 0) & (y < H) & ((y < 100) | (x % 20 < 10))
+
+
+def test_long_slab_lists(torch_cuda, bm):
+    """A comb of 1,500 teeth: each point inside its box pairs with slab lists
+    of 3,000 edges, so a round deals tens of thousands of edge chunks over
+    many windows. Equal to brute force (20k points and boundary points, edge
+    chunks of 4 and 16), and a pre-sorted call of 2^20 + 100 points equal to
+    the comb's closed form (which the oracle matches on the small set)."""
+    torch = torch_cuda
+    comb = _comb()
+    off, verts, ix = _rings_index(bm, [comb])
+    rng = np.random.default_rng(9)
+    pts = np.stack([rng.integers(900, 31100, 20000), rng.integers(900, 11100, 20000)], 1).astype(np.int32)
+    pts = np.concatenate([pts, comb, comb - 1, comb + 1]).astype(np.int32)
+    want = oracle.brute(off, verts, pts)
+    assert np.array_equal(want == 0, _comb_inside(pts))
+    for chunk in (4, 16):
+        say("comb, edge chunk", chunk)
+        got = gpu_map(bm, torch, ix, pts, tuning=bm.Tuning(chunk, 3, 2048, 1))
+        assert (got == want).all(), int((got != want).sum())
+    n = (1 << 20) + 100
+    big = np.stack([rng.integers(900, 31100, n), rng.integers(900, 11100, n)], 1).astype(np.int32)
+    say("comb, pre-sorted call of", n)
+    got = gpu_map(bm, torch, ix, big)
+    assert np.array_equal(got, np.where(_comb_inside(big), 0, -1).astype(got.dtype))
+
+
 def test_random_hierarchies_and_empty_groups(torch_cuda, bm):
     g = synth.geometry("grid1k")
     pts = np.concatenate([synth.points("grid1k", 20000), boundary_points(g, 500)])
