@@ -122,7 +122,7 @@ __device__ __forceinline__ int4 node_box(const KIndex& ix, int e) {
 // as a range [first, first + len) of `ent`; also the leaf's block index.
 __device__ __forceinline__ void slab_range(const KIndex& ix, const int leaf, const int py, unsigned& first,
                                            unsigned& len, unsigned& bid) {
-  const LeafRec* r = ix.leaf + leaf;
+  const LeafRec* r = reinterpret_cast<const LeafRec*>(reinterpret_cast<const char*>(ix.leaf) + ((unsigned)leaf << 6));
   const int4 meta = *reinterpret_cast<const int4*>(&r->ent);  // ent (2 words, below 2^31), leaf_id, packed
   const unsigned ent = (unsigned)meta.x;
   bid = (unsigned)meta.z;
@@ -208,23 +208,6 @@ __device__ __forceinline__ void emit(WaveLds& S, int dst, bool pred, unsigned no
   cnt += k;
 }
 
-// Where the boxes of one level live: node n's record starts at
-// rec + ((n - sub) << shift), its box first (groups: 32-byte records from
-// node 0, leaves: 64-byte records from leaf_base).
-struct LevelRecs {
-  const char* rec;
-  unsigned sub;
-  int shift;
-};
-
-__device__ __forceinline__ LevelRecs level_recs(const KIndex& ix, const bool leaves) {
-  LevelRecs L;
-  L.rec = leaves ? reinterpret_cast<const char*>(ix.leaf) : reinterpret_cast<const char*>(ix.grp);
-  L.sub = leaves ? (unsigned)ix.leaf_base : 0u;
-  L.shift = leaves ? 6 : 5;
-  return L;
-}
-
 // The plain path keeps the (group, point) items of all levels in one ring,
 // S.item[0] (kCap entries), consumed 64 per round in FIFO order whatever
 // their level, so the rounds run full; (leaf, point) pairs go to S.item[1].
@@ -304,10 +287,14 @@ __device__ __forceinline__ void emit2(WaveLds& S, const int dst, const bool p1, 
 __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
                                              const int4 gb, const int2 pp, int pl, unsigned& tail,
                                              const unsigned lim, unsigned& pcnt) {
+  // Group and leaf records share one allocation below 4 GB: node n's record
+  // is at byte ((n - sub) << shift) + adj from ix.grp, a 32-bit offset.
   const bool leaves = ci.x >= ix.leaf_base;
-  const char* rec = leaves ? reinterpret_cast<const char*>(ix.leaf) : reinterpret_cast<const char*>(ix.grp);
+  const char* recs = reinterpret_cast<const char*>(ix.grp);
   const unsigned sub = leaves ? (unsigned)ix.leaf_base : 0u;
-  const int shift = leaves ? 6 : 5;
+  const unsigned shift = leaves ? 6u : 5u;
+  const unsigned adj = leaves ? ix.leaf_off : 0u;
+  const char* masks = reinterpret_cast<const char*>(ix.slot_mask);  // below 2^29 words
   const int m = has ? ci.y - ci.x : 0;
   // children in windows of 128 (two 64-bit candidate words, lo then hi), so
   // that a lane's candidates of both words are taken in one loop
@@ -327,18 +314,20 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
           lo = hi = 0ull;
         } else {
           const unsigned w = (unsigned)base >> 6;
-          const unsigned long long* rx = ix.slot_mask + ((unsigned)ci.z + sx * W);
-          const unsigned long long* ry = ix.slot_mask + ((unsigned)ci.z + (S_ + sy) * W);
-          lo &= rx[w] & ry[w];
-          if (mm > 64) hi &= rx[w + 1] & ry[w + 1];
+          const unsigned ox = ((unsigned)ci.z + sx * W + w) << 3, oy = ((unsigned)ci.z + (S_ + sy) * W + w) << 3;
+          lo &= *reinterpret_cast<const unsigned long long*>(masks + ox) &
+                *reinterpret_cast<const unsigned long long*>(masks + oy);
+          if (mm > 64)
+            hi &= *reinterpret_cast<const unsigned long long*>(masks + ox + 8) &
+                  *reinterpret_cast<const unsigned long long*>(masks + oy + 8);
         }
       }
     }
     const unsigned c0 = (unsigned)(ci.x + base);
     // two candidates per lane and step: box tests, then the appends
     auto step = [&](const bool h1, const unsigned n1, const bool h2, const unsigned n2) {
-      const int4 bx1 = *reinterpret_cast<const int4*>(rec + ((size_t)(n1 - sub) << shift));
-      const int4 bx2 = *reinterpret_cast<const int4*>(rec + ((size_t)(n2 - sub) << shift));
+      const int4 bx1 = *reinterpret_cast<const int4*>(recs + (((n1 - sub) << shift) + adj));
+      const int4 bx2 = *reinterpret_cast<const int4*>(recs + (((n2 - sub) << shift) + adj));
       const bool in1 = h1 && in_box(bx1, pp), in2 = h2 && in_box(bx2, pp);
       emit2_ring(S, in1 && !leaves, n1, in2 && !leaves, n2, pl, tail, lim);
       emit2(S, 1, in1 && leaves, n1, in2 && leaves, n2, pl, pcnt);
@@ -489,7 +478,8 @@ __device__ __forceinline__ void map_tile_pts(const KIndex& ix, WaveLds& S, const
     const unsigned it = has ? S.item[0][q & (kCap - 1)] : 0u;  // lanes without an item read group 0
     head += min((unsigned)kWave, tail - head);
     wave_sync();  // this round's slots are free from here on
-    const GroupRec* g = ix.grp + (it >> kSlotBits);
+    const GroupRec* g =
+        reinterpret_cast<const GroupRec*>(reinterpret_cast<const char*>(ix.grp) + ((it >> kSlotBits) << 5));
     const int pl = (int)(it & (kTile - 1));
     expand_mixed(ix, S, has, g->child, g->box, S.pts[pl], pl, tail, head + kCap, pcnt);
     wave_sync();
