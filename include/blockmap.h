@@ -101,8 +101,7 @@ typedef struct {
  * by the caller until bm_index_destroy. Synchronous.
  * Errors: BM_EINVAL (null pointer, bad sizes or offsets, ring with fewer than
  * 3 or more than 2^24 vertices, parent out of range), BM_ERANGE (coordinate outside
- * [0, 2^31 - 1], more than 2^26 nodes, group and block records above 4 GB
- * (32 bytes per group, 64 per block), or slab edge lists of 2^31 or more
+ * [0, 2^31 - 1], more than 2^26 nodes, or slab edge lists of 2^31 or more
  * entries), BM_ENOMEM, BM_EHIP. */
 int bm_index_create(const bm_index_desc* desc, bm_index** out);
 

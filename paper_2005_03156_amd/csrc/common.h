@@ -54,7 +54,6 @@ static_assert(kTilePts == 1 || kTilePts == 2 || kTilePts == 4, "1, 2 or 4 points
 constexpr int kSlotBits = kTilePts == 4 ? 8 : kTilePts == 2 ? 7 : 6;
 constexpr long long kMaxNodes = 1ll << (32 - kSlotBits);
 constexpr long long kMaxEnt = (1ll << 31) - 64;
-constexpr long long kMaxRecordBytes = 1ll << 32;  // group and leaf records together
 constexpr long long kMaxSlotWords = 1ll << 29;    // slot-table words (byte offsets below 2^32)
 constexpr int kEntPad = 16;
 
@@ -70,8 +69,9 @@ struct KIndex {
   int32_t n_leaves;
   int4 root_child;            // the virtual root: its children are level 0
   int4 root_box;              // union of the level-0 boxes
-  uint32_t leaf_off;          // bytes from grp to leaf: both record arrays share one
-                              // allocation below 4 GB, so 32-bit offsets reach every record
+  uint32_t lbox_off;          // bytes from grp to the leaf boxes (int4 per leaf): the group
+                              // records and the leaf boxes share one allocation below 2^31
+                              // bytes, so 32-bit offsets reach every box a filter step tests
   long long presort_chunk;    // points per spatial-sort chunk (host side)
   int32_t presort_bin_bits;   // bins per axis of the sort: 2^5 or 2^6 (host side)
 };

@@ -33,10 +33,12 @@ constexpr int kTableLogSlots = 5;       // slots per axis: 32 (16 for up to 16 c
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 
-// Device layout of the records: the group records, then from a 64-byte
-// boundary the leaf records, in one allocation.
-size_t leaf_records_offset(const HostIndex& h) { return (h.grp.size() * sizeof(GroupRec) + 63) & ~(size_t)63; }
-size_t record_bytes(const HostIndex& h) { return leaf_records_offset(h) + h.leaf.size() * sizeof(LeafRec); }
+// Device layout of the boxes that filter steps test: the group records, then
+// from a 64-byte boundary a copy of every leaf's box (16 bytes, so that the
+// boxes of sibling leaves share cache lines), in one allocation. At most
+// 2^26 nodes keep it below 2^31 bytes.
+size_t leaf_boxes_offset(const HostIndex& h) { return (h.grp.size() * sizeof(GroupRec) + 63) & ~(size_t)63; }
+size_t box_block_bytes(const HostIndex& h) { return leaf_boxes_offset(h) + h.leaf.size() * sizeof(int4); }
 
 inline void grow(int4& a, const int4& b) {
   a.x = std::min(a.x, b.x);
@@ -318,8 +320,6 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
   for (int64_t e = 0; e < size[0]; ++e) grow(rb, box_of(e));
   if ((int64_t)h.ent.size() > kMaxEnt)
     return fail(BM_ERANGE, "bm_index_create: the slab edge lists exceed 2^31 entries");
-  if (record_bytes(h) > (size_t)kMaxRecordBytes)
-    return fail(BM_ERANGE, "bm_index_create: group and block records exceed 4 GB (32 B per group, 64 B per block)");
   h.root_box = rb;
   h.root_child = make_table(box_of, 0, (int)size[0], rb, h.slot_mask);
   h.n_levels = L;
@@ -355,9 +355,9 @@ int upload(bm_index* ix, const std::vector<T>& v, const T** dst, size_t pad = 0)
   return BM_OK;
 }
 
-int upload_records(bm_index* ix, const HostIndex& h, const GroupRec** grp, const LeafRec** leaf) {
+int upload_boxes(bm_index* ix, const HostIndex& h, const GroupRec** grp) {
   void* p = nullptr;
-  const size_t lo = leaf_records_offset(h), bytes = std::max<size_t>(record_bytes(h), 64);
+  const size_t lo = leaf_boxes_offset(h), bytes = std::max<size_t>(box_block_bytes(h), 64);
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     return fail(e == hipErrorOutOfMemory ? BM_ENOMEM : BM_EHIP,
@@ -366,12 +366,13 @@ int upload_records(bm_index* ix, const HostIndex& h, const GroupRec** grp, const
   ix->allocs[ix->n_allocs++] = p;
   ix->bytes += (int64_t)bytes;
   char* c = static_cast<char*>(p);
+  std::vector<int4> boxes(h.leaf.size());
+  for (size_t b = 0; b < h.leaf.size(); ++b) boxes[b] = h.leaf[b].box;
   if (!h.grp.empty()) e = hipMemcpy(c, h.grp.data(), h.grp.size() * sizeof(GroupRec), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !h.leaf.empty())
-    e = hipMemcpy(c + lo, h.leaf.data(), h.leaf.size() * sizeof(LeafRec), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !boxes.empty())
+    e = hipMemcpy(c + lo, boxes.data(), boxes.size() * sizeof(int4), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(BM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
   *grp = reinterpret_cast<const GroupRec*>(c);
-  *leaf = reinterpret_cast<const LeafRec*>(c + lo);
   return BM_OK;
 }
 
@@ -393,8 +394,9 @@ int make_device(HostIndex& h, bm_index** out) {
   if (e != hipSuccess || ix->num_cu < 1) ix->num_cu = 256;
   KIndex& k = ix->k;
   int rc = BM_OK;
-  if (rc == BM_OK) rc = upload_records(ix, h, &k.grp, &k.leaf);
-  k.leaf_off = (uint32_t)leaf_records_offset(h);
+  if (rc == BM_OK) rc = upload_boxes(ix, h, &k.grp);
+  if (rc == BM_OK) rc = upload(ix, h.leaf, &k.leaf);
+  k.lbox_off = (uint32_t)leaf_boxes_offset(h);
   if (rc == BM_OK) rc = upload(ix, h.ent, &k.ent, kEntPad);
   if (rc == BM_OK) rc = upload(ix, h.slot_mask, reinterpret_cast<const uint64_t**>(&k.slot_mask));
   if (rc == BM_OK) rc = upload(ix, h.parent, &k.parent);
@@ -443,9 +445,7 @@ bool consistent(const HostIndex& h) {
       (int64_t)h.leaf.size() != B || h.g0 > N || (h.n_levels == 0 ? h.g0 != B : h.g0 > lb))
     return false;
   const int64_t NE = (int64_t)h.ent.size();
-  if (N > kMaxNodes || NE > kMaxEnt || record_bytes(h) > (size_t)kMaxRecordBytes ||
-      (int64_t)h.slot_mask.size() > kMaxSlotWords)
-    return false;
+  if (N > kMaxNodes || NE > kMaxEnt || (int64_t)h.slot_mask.size() > kMaxSlotWords) return false;
   auto table_ok = [&](const int4& c) {
     if (c.z < 0) return true;
     const int logS = c.w & 0xff, shx = (c.w >> 8) & 0xff, shy = (c.w >> 16) & 0xff, m = c.y - c.x;

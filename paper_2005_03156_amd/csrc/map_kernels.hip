@@ -287,13 +287,14 @@ __device__ __forceinline__ void emit2(WaveLds& S, const int dst, const bool p1, 
 __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool has, const int4 ci,
                                              const int4 gb, const int2 pp, int pl, unsigned& tail,
                                              const unsigned lim, unsigned& pcnt) {
-  // Group and leaf records share one allocation below 4 GB: node n's record
-  // is at byte ((n - sub) << shift) + adj from ix.grp, a 32-bit offset.
+  // The boxes a step tests start at byte ((n - sub) << shift) + adj from
+  // ix.grp, a 32-bit offset: group n's record (32 bytes), or the copy of
+  // leaf n's box (16 bytes) in the array that follows the group records.
   const bool leaves = ci.x >= ix.leaf_base;
   const char* recs = reinterpret_cast<const char*>(ix.grp);
   const unsigned sub = leaves ? (unsigned)ix.leaf_base : 0u;
-  const unsigned shift = leaves ? 6u : 5u;
-  const unsigned adj = leaves ? ix.leaf_off : 0u;
+  const unsigned shift = leaves ? 4u : 5u;
+  const unsigned adj = leaves ? ix.lbox_off : 0u;
   const char* masks = reinterpret_cast<const char*>(ix.slot_mask);  // below 2^29 words
   const int m = has ? ci.y - ci.x : 0;
   // children in windows of 128 (two 64-bit candidate words, lo then hi), so
