@@ -149,6 +149,33 @@ def test_spatial_presort_never_changes_results(torch_cuda, bm, grid221k):
     assert (a.cpu().numpy()[sub] == H.map(pts[sub])).all()
 
 
+def test_concurrent_calls_on_several_streams(torch_cuda, bm, grid221k):
+    """The index is read-only and each call's scratch is its own (stream
+    ordered): calls queued on three streams at once, two of them pre-sorted,
+    give the ids of the same calls made one at a time, three times over."""
+    torch = torch_cuda
+    g, ix, H = grid221k
+    sizes = [(1 << 21) + 333, 50_000, (1 << 20) + 7]
+    xs = [torch.from_numpy(synth.points("grid221k", n, i0=30_000_000 + 5_000_000 * k)).cuda()
+          for k, n in enumerate(sizes)]
+    ref = [bm.map_points(ix, x) for x in xs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in sizes]
+    outs = [torch.empty_like(r) for r in ref]
+    for rep in range(3):
+        say("three streams, round", rep)
+        for o in outs:
+            o.fill_(-7)
+        torch.cuda.synchronize()
+        for st, x, o in zip(streams, xs, outs):
+            bm.map_points(ix, x, o, st)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r)
+    sub = np.random.default_rng(12).choice(sizes[0], 20_000, replace=False)
+    assert (ref[0].cpu().numpy()[sub] == H.map(xs[0].cpu().numpy()[sub])).all()
+
+
 @pytest.mark.parametrize("kind", ["one_point_inside", "one_point_outside", "vertical_line", "two_clusters"])
 def test_spatial_presort_degenerate_distributions(torch_cuda, bm, kind):
     """Pre-sorted calls whose points all fall in one bin (a single bin cut
