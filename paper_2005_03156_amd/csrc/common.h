@@ -17,8 +17,10 @@ namespace bm {
 // children of a group node form one contiguous id range, and consecutive
 // groups own consecutive ranges.
 //
-// Records are sized and aligned so that the box a parent level tests and the
-// data the next step needs share a cache line.
+// Records are sized and aligned so that each sits within one cache line: a
+// group's box beside its child record, a leaf's box beside what the crossing
+// test needs. Filter steps test leaf boxes from a compact copy (16 bytes per
+// leaf, after the group records; KIndex::lbox_off).
 struct alignas(32) GroupRec {
   int4 box;    // half-open (xmin, xmax, ymin, ymax), the union of the children's boxes
   int4 child;  // (first child, end of children, offset of the slot table in
