@@ -26,7 +26,8 @@ def sources():
 def build(verbose: bool = False, extra=None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + (extra or []) + sources() + ["-o", tmp, "-lpthread"]
+    cmd = [hipcc] + FLAGS + (extra or []) + sources() + ["-o", tmp, "-lpthread", "-L/opt/rocm/lib",
+                                                          "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "common.h"
+#include "trace.h"
 
 namespace bm {
 
@@ -71,6 +72,7 @@ extern "C" {
 
 __attribute__((visibility("default"))) int bm_index_create(const bm_index_desc* desc, bm_index** out) {
   try {
+    const TraceRange trace_range("bm_index_create");
     clear_error();
     return index_create(desc, out);
   }
@@ -114,6 +116,7 @@ __attribute__((visibility("default"))) int bm_index_build_file(const bm_index_de
 
 __attribute__((visibility("default"))) int bm_index_load(const char* path, bm_index** out) {
   try {
+    const TraceRange trace_range("bm_index_load");
     clear_error();
     return index_load(path, out);
   }
@@ -134,6 +137,7 @@ __attribute__((visibility("default"))) int map_points_tuned(const bm_index* inde
                                                            int32_t* out_ids, const bm_tuning* t,
                                                            hipStream_t stream) {
   try {
+    const TraceRange trace_range("map_points");
     if (!index) return fail(BM_EINVAL, "map_points: null index");
     if (n < 0) return fail(BM_EINVAL, "map_points: n < 0");
     if (n == 0) return BM_OK;
@@ -150,6 +154,7 @@ __attribute__((visibility("default"))) int map_points_tuned(const bm_index* inde
 __attribute__((visibility("default"))) int bm_cover_create(const bm_index* index, const bm_index_desc* desc,
                                                           const bm_cover_cfg* cfg, bm_cover** out) {
   try {
+    const TraceRange trace_range("bm_cover_create");
     if (index) {
       const int rc = check_device(index, "bm_cover_create");
       if (rc != BM_OK) return rc;
@@ -178,6 +183,7 @@ __attribute__((visibility("default"))) int bm_cover_build_file(const bm_index_de
 __attribute__((visibility("default"))) int map_points_cover(const bm_cover* cover, const int32_t* xy, int64_t n,
                                                            int32_t* out_ids, int32_t approx, hipStream_t stream) {
   try {
+    const TraceRange trace_range("map_points_cover");
     if (!cover) return fail(BM_EINVAL, "map_points_cover: null cover");
     if (n < 0) return fail(BM_EINVAL, "map_points_cover: n < 0");
     if (approx != 0 && approx != 1) return fail(BM_EINVAL, "map_points_cover: approx must be 0 or 1");
@@ -197,6 +203,7 @@ __attribute__((visibility("default"))) int map_points_cover(const bm_cover* cove
 __attribute__((visibility("default"))) int bm_count_per_block(const int32_t* ids, int64_t n, int64_t n_blocks,
                                                              uint64_t* counts, hipStream_t stream) {
   try {
+    const TraceRange trace_range("bm_count_per_block");
     if (n < 0 || n_blocks < 0 || n_blocks > INT32_MAX - 1) return fail(BM_EINVAL, "bm_count_per_block: bad size");
     if (!counts || (n > 0 && !ids)) return fail(BM_EINVAL, "bm_count_per_block: null buffer");
     if (n == 0) return BM_OK;
@@ -215,6 +222,7 @@ __attribute__((visibility("default"))) int map_points_timed(const bm_index* inde
                                                            int32_t* out_ids, const bm_tuning* t, hipStream_t stream,
                                                            bm_launch_times* times) {
   try {
+    const TraceRange trace_range("map_points_timed");
     if (!index || !times) return fail(BM_EINVAL, "map_points_timed: null argument");
     if (n < 0) return fail(BM_EINVAL, "map_points_timed: n < 0");
     if (n > 0 && (!xy || !out_ids)) return fail(BM_EINVAL, "map_points_timed: null buffer");
@@ -255,6 +263,7 @@ __attribute__((visibility("default"))) int map_points(const bm_index* index, con
 __attribute__((visibility("default"))) int bm_quantize_lonlat(const double* lonlat, int64_t n, int32_t* xy,
                                                              hipStream_t stream) {
   try {
+    const TraceRange trace_range("bm_quantize_lonlat");
     if (n < 0) return fail(BM_EINVAL, "bm_quantize_lonlat: n < 0");
     if (n == 0) return BM_OK;
     if (!lonlat || !xy) return fail(BM_EINVAL, "bm_quantize_lonlat: null buffer");

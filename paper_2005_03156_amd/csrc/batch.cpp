@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "common.h"
+#include "trace.h"
 
 using namespace bm;
 
@@ -80,6 +81,7 @@ extern "C" {
 __attribute__((visibility("default"))) int bm_map_batches(const bm_index* index, const bm_batch* batches,
                                                          int64_t nb, const bm_tuning* t, hipStream_t stream) {
   try {
+    const bm::TraceRange trace_range("bm_map_batches");
     clear_error();
     if (!index) return fail(BM_EINVAL, "bm_map_batches: null index");
     if (nb < 0) return fail(BM_EINVAL, "bm_map_batches: nb < 0");
@@ -153,6 +155,7 @@ __attribute__((visibility("default"))) int bm_batch_plan_create(const bm_index* 
 __attribute__((visibility("default"))) int bm_batch_plan_run(bm_batch_plan* p, const bm_batch* batches, int64_t nb,
                                                             hipStream_t stream) {
   try {
+    const bm::TraceRange trace_range("bm_batch_plan_run");
     clear_error();
     if (!p) return fail(BM_EINVAL, "bm_batch_plan_run: null plan");
     if (nb > p->max_batches) return fail(BM_EINVAL, "bm_batch_plan_run: more batches than the plan holds");
@@ -194,6 +197,7 @@ static std::string cache_path() {
 __attribute__((visibility("default"))) int bm_autotune(const bm_index* index, const int32_t* xy, int64_t n,
                                                       bm_tuning* out, hipStream_t stream) {
   try {
+    const bm::TraceRange trace_range("bm_autotune");
     clear_error();
     if (!index || !xy || !out) return fail(BM_EINVAL, "bm_autotune: null argument");
     if (n < 64) return fail(BM_EINVAL, "bm_autotune: need at least 64 sample points");

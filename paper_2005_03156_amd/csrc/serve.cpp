@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "common.h"
+#include "trace.h"
 
 using namespace bm;
 using Clock = std::chrono::steady_clock;
@@ -202,6 +203,7 @@ void bm_server::dispatch_loop() {
     lk.unlock();
 
     // stage, copy in, map, copy out: all queued on the slot's stream
+    bm::trace_push("server: dispatch batch");
     hipStream_t s = streams[nbatch++ % streams.size()];
     char* hx = h_pool + b->off;
     char* dx = d_pool + b->off;
@@ -252,6 +254,7 @@ void bm_server::dispatch_loop() {
     }
     flush_out(pos);
     if (e == hipSuccess) e = hipEventRecord(events[b->slot], s);
+    bm::trace_pop();
 
     lk.lock();
     if (e != hipSuccess) {
@@ -291,6 +294,7 @@ void bm_server::complete_loop() {
       continue;
     }
     lk.unlock();
+    bm::trace_push("server: retire batch");
     const int st = b->status;
     if (st == BM_OK) {
       const char* ho = h_pool + b->off + align_up(8 * b->npts);
@@ -302,6 +306,7 @@ void bm_server::complete_loop() {
       }
     }
     const auto now = Clock::now();
+    bm::trace_pop();
     lk.lock();
     inflight.erase(std::find(inflight.begin(), inflight.end(), b));
     alloc->release(b->off, b->bytes);
