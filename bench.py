@@ -81,8 +81,9 @@ def main():
                          "print its timing (a short run for the profiler)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the mapping path has no multi-GPU form here "
-              "(see DESIGN.md, 'Sharding'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the mapping path has no multi-GPU form here (points are "
+              "independent, so several GPUs would each map their own range against a copy of the "
+              "index); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

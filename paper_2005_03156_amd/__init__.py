@@ -28,8 +28,7 @@ class BlockmapError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libblockmap.so is not built (run __graft_entry__.build() or "
-                      "python paper_2005_03156_amd/build.py)")
+    raise ImportError("libblockmap.so is not built (run python paper_2005_03156_amd/build.py)")
 
 lib = C.CDLL(LIB_PATH)
 
