@@ -172,7 +172,9 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "census-scale plain mapping: 220,900 blocks (470x470 jittered grid, "
-                               "~24 vertices/block), 4-level hierarchy 50/3,000/70,000/220,900, "
+                               "~24 vertices/block), hierarchy 50 regions / 3,000 counties / 70,000 "
+                               "tracts / 220,900 blocks (the index merges the ~3-block tracts into "
+                               "their counties; all_levels_kept times all four), "
                                "100M int32 points (200-Gaussian mixture + 5% uniform)",
                    "points_per_step": n, "blocks": g.n_blocks},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
