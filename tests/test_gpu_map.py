@@ -264,10 +264,10 @@ def test_grid221k_full_size_sampled_and_partition_property(torch_cuda, bm, grid2
 
 # ----------------------------------------------------- hard inputs ----
 
-def _rings_index(bm, rings, n_groups=(), parents=()):
+def _rings_index(bm, rings, n_groups=(), parents=(), keep_all_levels=False):
     off = np.concatenate([[0], np.cumsum([len(r) for r in rings])]).astype(np.int64)
     verts = np.concatenate([np.asarray(r, np.int32) for r in rings])
-    return off, verts, bm.Index(off, verts, n_groups, parents)
+    return off, verts, bm.Index(off, verts, n_groups, parents, keep_all_levels=keep_all_levels)
 
 
 def test_nested_squares_overflow_fallback(torch_cuda, bm):
@@ -285,6 +285,16 @@ def test_nested_squares_overflow_fallback(torch_cuda, bm):
         want = oracle.brute(off, verts, pts)
         assert (got == want).all(), L
         assert (want > 300).any()
+    # two group levels, the finer one thin (pairs of squares): left out by
+    # default, kept on request, so the walk climbs one or two group levels
+    for keep in (False, True):
+        say("nested squares, thin level kept:", keep)
+        pair = (np.arange(K) // 2).astype(np.int32)
+        top = (np.arange(K // 2) % 7).astype(np.int32)
+        off, verts, ix = _rings_index(bm, rings, [7, K // 2], [top, pair], keep_all_levels=keep)
+        assert ix.info()["n_levels"] == (2 if keep else 1)
+        got = gpu_map(bm, torch_cuda, ix, pts)
+        assert (got == oracle.brute(off, verts, pts)).all(), keep
 
 
 def test_heavy_ring_and_many_small(torch_cuda, bm):
