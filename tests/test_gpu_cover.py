@@ -84,6 +84,25 @@ def test_cover_grid1k_exact_and_approx(torch_cuda, bm):
     assert (bm.map_points(ix, xy).cpu().numpy() == got).all()
 
 
+def test_cover_over_an_index_that_keeps_a_thin_level(torch_cuda, bm):
+    """The cover reads the leaf order from the index it is built on: over an
+    index that keeps a thin level (pairs of blocks under 16 groups), exact
+    cover lookups equal brute force and the index's own plain path."""
+    say("cover over an index with a kept thin level")
+    g = synth.geometry("grid1k")
+    pair = (np.arange(g.n_blocks) // 2).astype(np.int32)
+    top = (np.arange(g.n_blocks // 2) % 16).astype(np.int32)
+    ix = bm.Index(g.vert_off, g.verts, [16, g.n_blocks // 2], [top, pair], keep_all_levels=True)
+    assert ix.info()["n_levels"] == 2
+    cv = bm.Cover(ix, g.vert_off, g.verts)
+    rng = np.random.default_rng(5)
+    pts = np.concatenate([synth.points("grid1k", 30_000), boundary_points(g),
+                          grid_points(cv.info(), rng, 10_000)])
+    got, _ = check(bm, torch_cuda, cv, pts, lambda p: oracle.brute(g.vert_off, g.verts, p, box_reject=True))
+    xy = torch_cuda.from_numpy(pts).cuda()
+    assert (bm.map_points(ix, xy).cpu().numpy() == got).all()
+
+
 @pytest.mark.parametrize("cl", [7, 13])
 def test_cover_cell_sizes(torch_cuda, bm, cl):
     say("cover cell size", cl)
