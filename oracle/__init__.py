@@ -26,7 +26,7 @@ def build(force: bool = False) -> str:
     src = os.path.join(_HERE, "oracle.c")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", src,
+        subprocess.check_call(["gcc", "-O3", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", src,
                                "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -62,6 +62,10 @@ def _L():
         lib.orc_hier_destroy.argtypes = [P]
         lib.orc_hier_map.restype = None
         lib.orc_hier_map.argtypes = [P, i64, P, P, C.POINTER(Counts)]
+        lib.orc_count_per_block.restype = None
+        lib.orc_count_per_block.argtypes = [i64, P, i64, P]
+        lib.orc_join_per_block.restype = None
+        lib.orc_join_per_block.argtypes = [i64, P, i64, P, i64, P]
         lib.orc_threads.restype = C.c_int
         lib.orc_threads.argtypes = []
         lib.orc_set_threads.restype = None
@@ -113,6 +117,23 @@ def brute(vert_off, verts, xy, *, box_reject: bool = False, count_hits: bool = F
     hits = np.empty(n, np.int32) if count_hits else None
     _L().orc_brute(nb, _p(vo), _p(vv), _p(box), n, _p(pts), _p(out), _p(hits))
     return (out, hits) if count_hits else out
+
+
+def count_per_block(ids, n_blocks: int) -> np.ndarray:
+    """Points per block: entry b counts the ids equal to b, entry n_blocks the
+    others (-1, no block)."""
+    a = _c(ids, np.int32)
+    counts = np.zeros(int(n_blocks) + 1, np.uint64)
+    _L().orc_count_per_block(a.shape[0], _p(a), int(n_blocks), _p(counts))
+    return counts
+
+
+def join_per_block(ids, table, fill: int = -1) -> np.ndarray:
+    """Per-point join: table[id] for ids in [0, len(table)), else fill."""
+    a, t = _c(ids, np.int32), _c(table, np.int64)
+    out = np.empty(a.shape[0], np.int64)
+    _L().orc_join_per_block(a.shape[0], _p(a), t.shape[0], _p(t), int(fill), _p(out))
+    return out
 
 
 class Hier:

@@ -256,6 +256,31 @@ ORC_API void orc_hier_map(const orc_hier* h, int64_t n, const int32_t* xy, int32
   if (counts) *counts = tot;
 }
 
+/* ------------------------------------------------ per-block aggregation ---- */
+
+/* Points per block, the count that the paper's purpose (Sec. I-II: merging
+ * demographic data by block) starts from: counts[b] += number of i with
+ * ids[i] == b, for b in [0, nb); counts[nb] += number of the other ids (-1,
+ * no block). counts holds nb + 1 entries and is accumulated into. */
+ORC_API void orc_count_per_block(int64_t n, const int32_t* ids, int64_t nb, uint64_t* counts) {
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t b = ids[i];
+    if (b >= 0 && b < nb) counts[b]++;
+    else counts[nb]++;
+  }
+}
+
+/* Per-point join of a per-block attribute (App. A gathers each point's block
+ * FIPS code from the block's record): out[i] = table[ids[i]] when ids[i] is in
+ * [0, nb), else fill. */
+ORC_API void orc_join_per_block(int64_t n, const int32_t* ids, int64_t nb, const int64_t* table,
+                                int64_t fill, int64_t* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t b = ids[i];
+    out[i] = (b >= 0 && b < nb) ? table[b] : fill;
+  }
+}
+
 /* Number of worker threads OpenMP will use (for reporting). */
 #ifdef _OPENMP
 #include <omp.h>

@@ -321,3 +321,142 @@ def test_quantizer_monotone_and_resolution():
     back = (q - 2**30) / 2**22
     assert np.abs(back[:, 0] - lon).max() <= 2.0**-23
     assert np.abs(back[:, 1] - lat).max() <= 2.0**-23
+
+
+# ------------------------------------------------------- work counters ----
+#
+# The hierarchy route counts its work (Sec. III's box tests level by level,
+# Sec. III-A's edge tests), and those counts price the method per point. On a
+# sheared grid every count has a closed form: cell (i, j) is the
+# parallelogram with corners (i c + j s, j c), ((i+1) c + j s, j c),
+# ((i+1) c + (j+1) s, (j+1) c), (i c + (j+1) s, (j+1) c), each side cut into
+# k + 1 equal collinear pieces. Its half-open box is
+# [i c + j s, (i+1) c + (j+1) s) x [j c, (j+1) c); a group of g x g cells has
+# the same shape with c, s scaled by g.
+
+SHEAR = dict(n=24, c=600, s=240, k=2, mid=3, top=2)  # c and s divisible by k + 1
+
+
+def _sheared_grid(n, c, s, k, mid, top):
+    rings = []
+    for j in range(n):
+        for i in range(n):
+            A = (i * c + j * s, j * c)
+            B = ((i + 1) * c + j * s, j * c)
+            Cc = ((i + 1) * c + (j + 1) * s, (j + 1) * c)
+            D = (i * c + (j + 1) * s, (j + 1) * c)
+            ring = []
+            for P, Q in ((A, B), (B, Cc), (Cc, D), (D, A)):
+                for q in range(k + 1):  # P and the k interior points of side P->Q
+                    ring.append((P[0] + (Q[0] - P[0]) * q // (k + 1), P[1] + (Q[1] - P[1]) * q // (k + 1)))
+            rings.append(ring)
+    off = np.concatenate([[0], np.cumsum([len(r) for r in rings])]).astype(np.int64)
+    verts = np.asarray([v for r in rings for v in r], np.int32)
+    nm, nt = n // mid, n // (mid * top)
+    jj, ii = np.divmod(np.arange(n * n), n)
+    par_cells = ((jj // mid) * nm + ii // mid).astype(np.int32)
+    mj, mi = np.divmod(np.arange(nm * nm), nm)
+    par_mid = ((mj // top) * nt + mi // top).astype(np.int32)
+    return off, verts, [nt * nt, nm * nm], [par_mid, par_cells]
+
+
+def _boxes_holding(px, py, C, S, nI, nJ):
+    """Number of boxes [I C + J S, (I+1) C + (J+1) S) x [J C, (J+1) C),
+    0 <= I < nI, 0 <= J < nJ, that hold each point, and the first such I."""
+    J = py // C
+    lo = (px - (J + 1) * S) // C  # smallest I with (I+1) C + (J+1) S > px
+    hi = (px - J * S) // C        # largest I with I C + J S <= px
+    lo_c, hi_c = np.maximum(lo, 0), np.minimum(hi, nI - 1)
+    cnt = np.where((py >= 0) & (J < nJ), np.maximum(hi_c - lo_c + 1, 0), 0)
+    return cnt, lo_c
+
+
+def _closed_form_counts(pts, n, c, s, k, mid, top):
+    px, py = pts[:, 0].astype(np.int64), pts[:, 1].astype(np.int64)
+    nm, nt = n // mid, n // (mid * top)
+    top_hit, _ = _boxes_holding(px, py, c * mid * top, s * mid * top, nt, nt)
+    mid_hit, _ = _boxes_holding(px, py, c * mid, s * mid, nm, nm)
+    leaf, first = _boxes_holding(px, py, c, s, n, n)
+    m = 4 * (k + 1)
+    bbox = nt * nt + top * top * top_hit + mid * mid * mid_hit
+    # one piece of each slanted side straddles the point's row: piece q of
+    # the left side of cell i spans x in [i c + j s + q s', i c + j s + (q+1) s']
+    sp = s // (k + 1)
+    j = py // c
+    q = (py - j * c) * (k + 1) // c
+    xamb = np.zeros_like(px)
+    for d in range(2):  # s < c: at most two candidate cells per point
+        i = first + d
+        valid = d < leaf
+        for side in (0, 1):  # left side of cell i, then its right side
+            lo = (i + side) * c + j * s + q * sp
+            xamb += (valid & (lo <= px) & (px < lo + sp)).astype(np.int64)
+    inside = (py >= 0) & (py < n * c) & (px * c >= py * s) & (px * c < py * s + n * c * c)
+    return {"bbox_tests": bbox, "leaf_cands": leaf, "edge_tests": leaf * m, "straddles": 2 * leaf,
+            "x_ambiguous": xamb, "hits": inside.astype(np.int64)}
+
+
+def _shear_points(n, c, s, **_):
+    rng = np.random.default_rng(31)
+    W = n * c + n * s
+    pts = rng.integers(-200, W + 200, (6000, 2))
+    pts[:, 1] = rng.integers(-200, n * c + 200, 6000)
+    # lattice corners, interior side points and their neighbours
+    jj, ii = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    corner = np.stack([ii * c + jj * s, jj * c], -1).reshape(-1, 2)
+    near = (corner[:, None, :] + np.array([[0, 0], [-1, 0], [0, -1], [1, 0], [0, 1], [1, 1], [-1, -1]])).reshape(-1, 2)
+    piece = corner[:, None, :] + np.array([[s // 3, c // 3], [s // 3 - 1, c // 3], [2 * s // 3, 2 * c // 3]])
+    return np.concatenate([pts, near, piece.reshape(-1, 2)]).astype(np.int32)
+
+
+def test_hierarchy_work_counts_closed_form():
+    """Every counter of the hierarchy route (box tests at each level, blocks
+    reaching the crossing test, ring edges examined, straddling edges, edges
+    whose x-range holds the point, hits) equals its closed form on a sheared
+    grid, point by point on a sample and in total over all points."""
+    off, verts, ng, par = _sheared_grid(**SHEAR)
+    pts = _shear_points(**SHEAR)
+    want = _closed_form_counts(pts, **SHEAR)
+    H = oracle.Hier(off, verts, ng, par)
+    ids, tot = H.map(pts, with_counts=True)
+    for key, arr in want.items():
+        assert tot[key] == int(arr.sum()), (key, tot[key], int(arr.sum()))
+    assert (want["x_ambiguous"] > 0).sum() > 100 and (want["leaf_cands"] == 2).sum() > 100
+    sub = np.random.default_rng(2).choice(pts.shape[0], 400, replace=False)
+    for i in sub:
+        _, one = H.map(pts[i:i + 1], with_counts=True)
+        for key, arr in want.items():
+            assert one[key] == int(arr[i]), (key, pts[i], one[key], int(arr[i]))
+    assert ((ids >= 0) == (want["hits"] == 1)).all()
+
+
+# ------------------------------------------------- per-block aggregation ----
+
+def test_count_and_join_per_block_closed_form():
+    """On the un-jittered grid, a lattice of q x q points inside every cell puts
+    exactly q^2 points in each block, and points outside land in the last
+    entry; a per-block code table joined per point gives the code of the
+    point's cell, floor(y/c) * 1000 + floor(x/c), or the fill value."""
+    n, c, q = 10, 1000, 3
+    off, verts = synth.jittered_grid(n, c, kmin=1, kmax=4, vjit=0.0, pjit=0.0, key_=5)
+    u = (np.arange(q) * (c // q) + 7)
+    cx, cy = np.meshgrid(np.arange(n) * c, np.arange(n) * c)
+    ux, uy = np.meshgrid(u, u)
+    lattice = np.stack([(cx.ravel()[:, None] + ux.ravel()[None]).ravel(),
+                        (cy.ravel()[:, None] + uy.ravel()[None]).ravel()], 1)
+    outside = np.array([[-1, 5], [n * c, 3], [4, n * c], [-7, -7], [n * c + 9, n * c + 9]])
+    pts = np.concatenate([lattice, outside]).astype(np.int32)
+    pts = pts[np.random.default_rng(3).permutation(pts.shape[0])]
+    ids = oracle.brute(off, verts, pts)
+    counts = oracle.count_per_block(ids, n * n)
+    assert (counts[:-1] == q * q).all() and counts[-1] == outside.shape[0]
+    assert counts.sum() == pts.shape[0]
+    # accumulation: a second call adds
+    ids2 = np.array([0, 0, -1, n * n, 5], np.int32)
+    c2 = oracle.count_per_block(ids2, n * n)
+    assert c2[0] == 2 and c2[5] == 1 and c2[-1] == 2 and c2.sum() == 5
+    table = np.array([(b // n) * 1000 + b % n for b in range(n * n)], np.int64)
+    got = oracle.join_per_block(ids, table, fill=-99)
+    x, y = pts[:, 0].astype(np.int64), pts[:, 1].astype(np.int64)
+    ins = (x >= 0) & (x < n * c) & (y >= 0) & (y < n * c)
+    assert (got == np.where(ins, (y // c) * 1000 + x // c, -99)).all()
