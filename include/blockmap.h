@@ -414,6 +414,17 @@ int map_points_cover(const bm_cover* cover, const int32_t* xy, int64_t n, int32_
  * Errors: BM_EINVAL (null buffer, n < 0, n_blocks outside [0, 2^31 - 2]), BM_EHIP. */
 int bm_count_per_block(const int32_t* ids, int64_t n, int64_t n_blocks, uint64_t* counts, hipStream_t stream);
 
+/* Per-point join of a per-block attribute: App. A ends by giving each point
+ * the FIPS code of its block, the key on which the census tables of Sec. I-II
+ * are merged. For ids[0..n) (device, as written by map_points) and table
+ * (device, n_blocks int64, e.g. numeric block FIPS codes), writes out[i] =
+ * table[ids[i]] when ids[i] is in [0, n_blocks), else fill (device, n int64,
+ * caller-owned; must not overlap ids or table). Asynchronous on `stream`; no
+ * scratch. table may be null when n_blocks = 0.
+ * Errors: BM_EINVAL (null buffer, n < 0, n_blocks outside [0, 2^31 - 2]), BM_EHIP. */
+int bm_join_per_block(const int32_t* ids, int64_t n, const int64_t* table, int64_t n_blocks, int64_t fill,
+                      int64_t* out, hipStream_t stream);
+
 /* Error text for the last failing call on this thread ("" if none). */
 const char* bm_last_error(void);
 

@@ -138,6 +138,7 @@ _SIGS = {
     "bm_cover_build_file": (C.c_int, [C.POINTER(IndexDesc), C.POINTER(CoverCfg), C.c_char_p]),
     "map_points_cover": (C.c_int, [_P, _P, _I64, _P, C.c_int32, _P]),
     "bm_count_per_block": (C.c_int, [_P, _I64, _I64, _P, _P]),
+    "bm_join_per_block": (C.c_int, [_P, _I64, _P, _I64, _I64, _P, _P]),
     "bm_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -341,13 +342,19 @@ def count_per_block(ids, n_blocks: int, counts=None, stream=None):
     return counts
 
 
-def join_per_block(counts, table):
-    """Host join of per-block counts with a per-block attribute table (e.g. the
-    blocks' FIPS codes or demographic columns, indexed by block): rows of
-    (attribute, count) for the blocks with at least one point."""
-    c = counts[:-1].cpu().numpy() if hasattr(counts, "cpu") else np.asarray(counts)[:-1]
-    nz = np.nonzero(c)[0]
-    return np.asarray(table)[nz], c[nz]
+def join_per_block(ids, table, out=None, fill: int = -1, stream=None):
+    """Per-point join on the device: out[i] = table[ids[i]] for ids in
+    [0, len(table)), else fill. `ids` is a CUDA int32 tensor, `table` a CUDA
+    int64 tensor of per-block attributes (e.g. numeric FIPS codes); returns
+    (or fills) a CUDA int64 tensor of len(ids)."""
+    import torch
+    if out is None:
+        out = torch.empty(ids.shape[0], dtype=torch.int64, device=ids.device)
+    if out.shape[0] != ids.shape[0]:
+        raise ValueError("out must hold one entry per id")
+    _check(lib.bm_join_per_block(_dev_ptr(ids, "int32"), ids.shape[0], _dev_ptr(table, "int64"), table.shape[0],
+                                 int(fill), _dev_ptr(out, "int64"), _stream_handle(stream)))
+    return out
 
 
 def map_points_timed(index: Index, xy, out, stream=None, tuning: Tuning | None = None) -> dict:

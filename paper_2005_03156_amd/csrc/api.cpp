@@ -218,6 +218,25 @@ __attribute__((visibility("default"))) int bm_count_per_block(const int32_t* ids
   BM_GUARD("bm_count_per_block")
 }
 
+__attribute__((visibility("default"))) int bm_join_per_block(const int32_t* ids, int64_t n, const int64_t* table,
+                                                            int64_t n_blocks, int64_t fill, int64_t* out,
+                                                            hipStream_t stream) {
+  try {
+    const TraceRange trace_range("bm_join_per_block");
+    if (n < 0 || n_blocks < 0 || n_blocks > INT32_MAX - 1) return fail(BM_EINVAL, "bm_join_per_block: bad size");
+    if (n > 0 && (!ids || !out || (n_blocks > 0 && !table)))
+      return fail(BM_EINVAL, "bm_join_per_block: null buffer");
+    if (n == 0) return BM_OK;
+    int dev = 0, num_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = launch_join(ids, n, table, (int32_t)n_blocks, fill, out, std::max(1, num_cu), stream);
+    if (e != hipSuccess) return fail(BM_EHIP, std::string("bm_join_per_block: launch: ") + hipGetErrorString(e));
+    return BM_OK;
+  }
+  BM_GUARD("bm_join_per_block")
+}
+
 __attribute__((visibility("default"))) int map_points_timed(const bm_index* index, const int32_t* xy, int64_t n,
                                                            int32_t* out_ids, const bm_tuning* t, hipStream_t stream,
                                                            bm_launch_times* times) {

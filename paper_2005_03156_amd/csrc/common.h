@@ -157,6 +157,8 @@ hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, 
 hipError_t launch_quantize(const double* lonlat, int64_t n, int32_t* xy, int num_cu,
                            hipStream_t stream);
 // Points per block into counts[0 .. nb] (the last slot: ids outside [0, nb)).
+hipError_t launch_join(const int32_t* ids, int64_t n, const int64_t* table, int32_t nb, int64_t fill, int64_t* out,
+                       int num_cu, hipStream_t stream);
 hipError_t launch_count(const int32_t* ids, int64_t n, int32_t nb, unsigned long long* counts, int num_cu,
                         hipStream_t stream);
 // Cover form: every point looked up in the cell trie; boundary cells resolved

@@ -306,3 +306,60 @@ def quadtree_geometry(**q) -> Geometry:
     n_groups = [(R // 64) ** 2, (R // 8) ** 2, R * R, ng]
     return Geometry(off, verts, n_groups, parents, W=R << q["lg_cell"], name="quadtree8m",
                     meta=dict(depth=depth.reshape(R, R), leaf_off=leaf_off))
+
+
+def block_codes(g: Geometry) -> np.ndarray:
+    """A numeric code per block composed like a census FIPS code: the top
+    group's number (from 1), then at every level the entity's rank among its
+    parent's children in index order, each level in as many decimal digits as
+    its largest family needs. A per-block attribute table for the join; it
+    depends only on the hierarchy arrays."""
+    if not g.parents:
+        return np.arange(g.n_blocks, dtype=np.int64)
+    code = np.arange(1, int(g.n_groups[0]) + 1, dtype=np.int64)
+    total_digits = len(str(int(g.n_groups[0])))
+    for par in g.parents:
+        par = np.asarray(par, np.int64)
+        counts = np.bincount(par, minlength=code.shape[0])
+        digits = len(str(max(int(counts.max()) - 1, 0)))
+        total_digits += digits
+        if total_digits > 18:
+            raise ValueError("codes would not fit in 63 bits")
+        order = np.argsort(par, kind="stable")
+        first = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        rank = np.empty(par.shape[0], np.int64)
+        rank[order] = np.arange(par.shape[0]) - first[par[order]]
+        code = code[par] * (10 ** digits) + rank
+    return code
+
+# ------------------------------------------- batched and served workloads ----
+
+def batch_sizes(nb: int = 10_000, hi: float = 1e6) -> np.ndarray:
+    """Sizes of the batched workload's batches: round(exp(U[0, ln hi]))."""
+    return sizes(key("batches10k", 2, 0), nb, 0, 0.0, 0.0, hi)
+
+
+def batch_points(g: Geometry, sizes_: np.ndarray, first: int = 1, out: np.ndarray | None = None):
+    """The batched workload's points: batch b (key first + b) is one Gaussian
+    cluster (centre uniform over the extent, sigma log-uniform on [0.1%, 5%]
+    of it). Returns the concatenation (int32 [sum, 2]) and the batch offsets
+    (int64 [nb + 1])."""
+    off = np.concatenate([[0], np.cumsum(sizes_)]).astype(np.int64)
+    out = np.empty((int(off[-1]), 2), np.int32) if out is None else out
+    for b in range(len(sizes_)):
+        m = Mixture(key("batches10k", 2, first + b), 1, g.W, 0.0, 0.001, 0.05, 0.0)
+        m.sample(key("batches10k", 3, first + b), 0, int(sizes_[b]), out=out[off[b]:off[b + 1]])
+    return out, off
+
+
+def request_sizes(n: int, first: int = 0, median: float = 10_000.0, s: float = 2.0, hi: float = 10_000_000):
+    """Sizes of served requests: lognormal (median 10k, sigma_ln 2), clamped
+    to [1, hi]."""
+    return sizes(key("requests20k", 2, first), n, 1, median, s, hi)
+
+
+def request_points(g: Geometry, r: int, n: int, out: np.ndarray | None = None) -> np.ndarray:
+    """Request r of the served workload: one Gaussian cluster (sigma
+    log-uniform on [0.1%, 2%] of the extent) plus 20% uniform points."""
+    m = Mixture(key("requests20k", 2, r + 1), 1, g.W, 0.0, 0.001, 0.02, 0.2)
+    return m.sample(key("requests20k", 3, r + 1), 0, int(n), out)

@@ -229,10 +229,10 @@ def test_spatial_presort_small_root_box(torch_cuda, bm, side):
     assert (a.cpu().numpy()[sub] == oracle.brute(off, verts, pts[sub])).all()
 
 
-def test_grid221k_full_size_sampled_and_partition_property(torch_cuda, bm, grid221k):
-    """100M points in the benchmark's launch shape: sampled outputs against the
-    oracle, and at every point the partition property (an id exactly when the
-    point lies in [0, W)^2)."""
+def test_grid221k_full_size_every_point(torch_cuda, bm, grid221k):
+    """100M points in the benchmark's launch shape: every output equals the
+    hierarchy oracle's, the partition property holds at every point (an id
+    exactly when the point lies in [0, W)^2), and a sample equals brute force."""
     torch = torch_cuda
     g, ix, H = grid221k
     n = synth.n_points("grid221k")
@@ -242,13 +242,15 @@ def test_grid221k_full_size_sampled_and_partition_property(torch_cuda, bm, grid2
     out = bm.map_points(ix, xy)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    say("grid221k full size: checking")
+    say("grid221k full size: oracle over every point")
+    want = H.map(pts)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, (bad.size, bad[:5], got[bad[:5]], want[bad[:5]])
     x, y = pts[:, 0], pts[:, 1]
     inside = (x >= 0) & (x < g.W) & (y >= 0) & (y < g.W)
     assert ((got >= 0) == inside).all()
-    assert (got < g.n_blocks).all()
-    sub = np.random.default_rng(7).choice(n, 200_000, replace=False)
-    assert (got[sub] == H.map(pts[sub])).all()
+    sub = np.random.default_rng(7).choice(n, 2000, replace=False)
+    assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all()
     # a repeat run gives identical bytes
     out2 = bm.map_points(ix, xy)
     torch.cuda.synchronize()
@@ -461,78 +463,114 @@ def test_quantized_points_map_like_the_oracle(torch_cuda, bm):
 
 # ------------------------------------------------------------ quadtree8m ----
 
-def test_quadtree8m_streamed_billion_points(torch_cuda, bm):
-    """8M-block graded mesh, 1B points in 2^26-point chunks: every output obeys
-    the partition property, a full 8M slice equals the hierarchy oracle, and
-    sampled points equal brute force."""
-    torch = torch_cuda
-    say("quadtree8m: generating geometry")
+QT_CHUNKS = (synth.QUADTREE["n_points"] + synth.QUADTREE["chunk"] - 1) // synth.QUADTREE["chunk"]
+
+
+@pytest.fixture(scope="module")
+def quadtree8m(bm, torch_cuda):
+    say("quadtree8m: generating geometry, index and oracle hierarchy")
     g = synth.geometry("quadtree8m")
-    ix = bm.Index.from_geometry(g)
-    H = oracle.Hier.from_geometry(g)
+    return g, bm.Index.from_geometry(g), oracle.Hier.from_geometry(g)
+
+
+@pytest.mark.parametrize("k", range(QT_CHUNKS))
+def test_quadtree8m_chunk_every_point(torch_cuda, bm, quadtree8m, k):
+    """Chunk k of the 1B-point stream over the 8M-block graded mesh (2^26
+    points, one resident call as the benchmark maps it): every output equals
+    the hierarchy oracle's, the partition property holds at every point, and a
+    sample equals brute force. Together the chunks cover all 1B points."""
+    torch = torch_cuda
+    g, ix, H = quadtree8m
     q = synth.QUADTREE
     N, CH = q["n_points"], q["chunk"]
-    rng = np.random.default_rng(12)
-    out = torch.empty(CH, dtype=torch.int32, device="cuda")
-    kept = []
-    for k in range((N + CH - 1) // CH):
-        n = min(CH, N - k * CH)
-        pts = synth.points("quadtree8m", n, i0=k * CH)
-        xy = torch.from_numpy(pts).cuda()
-        bm.map_points(ix, xy, out[:n])
-        got = out[:n].cpu().numpy()
-        if k < 2:
-            kept.append((xy, got))
-        x, y = pts[:, 0], pts[:, 1]
-        inside = (x >= 0) & (x < g.W) & (y >= 0) & (y < g.W)
-        assert ((got >= 0) == inside).all(), k
-        sub = rng.choice(n, 300, replace=False)
-        assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all(), k
-        if k == 0:
-            assert (got[:8_000_000] == H.map(pts[:8_000_000])).all()
-        say("quadtree8m chunk", k, "ok", n)
-    # one call over two chunks and a ragged tail (2^27 + 12,345 points): with
-    # this index's size the sort runs in 2^26-point chunks, two rounds of sort
-    # passes
-    extra = 12_345
+    n = min(CH, N - k * CH)
+    say("quadtree8m chunk", k, "of", QT_CHUNKS, ":", n, "points")
+    pts = synth.points("quadtree8m", n, i0=k * CH)
+    got = bm.map_points(ix, torch.from_numpy(pts).cuda()).cpu().numpy()
+    want = H.map(pts)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, (k, bad.size, bad[:5], got[bad[:5]], want[bad[:5]])
+    x, y = pts[:, 0], pts[:, 1]
+    inside = (x >= 0) & (x < g.W) & (y >= 0) & (y < g.W)
+    assert ((got >= 0) == inside).all(), k
+    sub = np.random.default_rng(12 + k).choice(n, 100, replace=False)
+    assert (got[sub] == oracle.brute(g.vert_off, g.verts, pts[sub], box_reject=True)).all(), k
+
+
+def test_quadtree8m_one_call_over_several_chunks(torch_cuda, bm, quadtree8m):
+    """One call over two chunks and a ragged tail (2^27 + 12,345 points): with
+    this index's size the sort runs in 2^26-point chunks, two rounds of sort
+    passes; the result equals the per-chunk calls and, on the tail, the
+    oracle."""
+    torch = torch_cuda
+    g, ix, H = quadtree8m
+    CH, extra = synth.QUADTREE["chunk"], 12_345
+    xs = [torch.from_numpy(synth.points("quadtree8m", CH, i0=k * CH)).cuda() for k in range(2)]
+    per = [bm.map_points(ix, x) for x in xs]
     say("quadtree8m: one call of", 2 * CH + extra)
-    both = bm.map_points(ix, torch.cat([kept[0][0], kept[1][0], kept[0][0][:extra]])).cpu().numpy()
-    assert (both[:CH] == kept[0][1]).all() and (both[CH:2 * CH] == kept[1][1]).all()
-    assert (both[2 * CH:] == kept[0][1][:extra]).all()
+    both = bm.map_points(ix, torch.cat([xs[0], xs[1], xs[0][:extra]]))
+    torch.cuda.synchronize()
+    assert torch.equal(both[:CH], per[0]) and torch.equal(both[CH:2 * CH], per[1])
+    assert torch.equal(both[2 * CH:], per[0][:extra])
+    tail = xs[0][:extra].cpu().numpy()
+    assert (both[2 * CH:].cpu().numpy() == H.map(tail)).all()
 
 
 # ------------------------------------------------------- batched form ----
 
 def _cluster_batches(g, sizes, seed):
     """One Gaussian cluster per batch (the batched workload's recipe)."""
-    out = []
-    for b, n in enumerate(sizes):
-        m = synth.Mixture(synth.key("batches10k", 2, seed * 100000 + b), 1, g.W, 0.0, 0.001, 0.05, 0.0)
-        out.append(m.sample(synth.key("batches10k", 3, seed * 100000 + b), 0, int(n)))
-    return out
+    allp, off = synth.batch_points(g, np.asarray(sizes), first=seed * 100000)
+    return [allp[off[b]:off[b + 1]] for b in range(len(sizes))]
 
 
-def test_batched_equals_plain_per_batch(torch_cuda, bm, grid221k):
+def test_batched_equals_oracle_and_plain(torch_cuda, bm, grid221k):
+    """Batches of 0 to 200k points in one persistent launch, for three tile
+    sizes: every output equals the hierarchy oracle's, and the plain path's
+    per-batch result."""
     torch = torch_cuda
     g, ix, H = grid221k
     sizes = synth.sizes(synth.key("batches10k", 2, 0), 300, 0, 0, 0, 200_000)
     sizes[:5] = [0, 1, 63, 64, 65]
     say("batched: %d batches, %d points" % (len(sizes), sizes.sum()))
     pts = _cluster_batches(g, sizes, 1)
+    want = H.map(np.concatenate(pts))
     xys = [torch.from_numpy(p).cuda() for p in pts]
-    want = [bm.map_points(ix, xy) for xy in xys]
-    torch.cuda.synchronize()
+    plain = torch.cat([bm.map_points(ix, xy) for xy in xys]).cpu().numpy()
+    assert np.array_equal(plain, want)
     for tile in (64, 1024, 8192):
         outs = [torch.full((p.shape[0],), -7, dtype=torch.int32, device="cuda") for p in pts]
         tab = bm.batch_table(xys, outs)
         bm.map_batches(ix, tab, tuning=bm.Tuning(8, 4, tile))
         torch.cuda.synchronize()
-        for w, o in zip(want, outs):
-            assert torch.equal(w, o), tile
-    allp = np.concatenate(pts)
-    sub = np.random.default_rng(3).choice(allp.shape[0], 20000, replace=False)
-    got = torch.cat(want).cpu().numpy()
-    assert (got[sub] == H.map(allp[sub])).all()
+        got = torch.cat(outs).cpu().numpy()
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, (tile, bad.size, bad[:5])
+
+
+def test_batched_full_size_every_point(torch_cuda, bm, grid221k):
+    """The batched workload at full size (10,000 batches of 1 to 1M points,
+    729M points over the census-scale index), through the captured graph as
+    the benchmark replays it: every output equals the hierarchy oracle's."""
+    torch = torch_cuda
+    g, ix, H = grid221k
+    sizes = synth.batch_sizes()
+    say("batched full size: generating", int(sizes.sum()), "points")
+    host, off = synth.batch_points(g, sizes)
+    xy = torch.from_numpy(host).cuda()
+    out = torch.full((host.shape[0],), -7, dtype=torch.int32, device="cuda")
+    rows = [(xy.data_ptr() + 8 * int(off[b]), out.data_ptr() + 4 * int(off[b]), int(sizes[b]))
+            for b in range(len(sizes))]
+    plan = bm.BatchPlan(ix, len(sizes), bm.Tuning(4, 8, 512))
+    plan.run_rows(bm.make_rows(rows), len(sizes), torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    plan.close()
+    got = out.cpu().numpy()
+    del xy, out
+    say("batched full size: oracle over every point")
+    want = H.map(host)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, (bad.size, bad[:5], got[bad[:5]], want[bad[:5]])
 
 
 def test_batch_plan_graph_replays(torch_cuda, bm, grid221k):
@@ -654,3 +692,32 @@ def test_server_poisson_trace(torch_cuda, bm, grid221k):
     allo = np.concatenate(outs)
     sub = np.random.default_rng(1).choice(allp.shape[0], 50_000, replace=False)
     assert (allo[sub] == H.map(allp[sub])).all()
+
+
+def test_server_over_quadtree8m_every_point(torch_cuda, bm, quadtree8m):
+    """The served workload's setting: the 8M-block mesh resident in HBM,
+    requests of lognormal size (median 10k points, sigma_ln 2, capped at 2M
+    here), each a cluster plus 20% uniform points with its own output buffer,
+    under Poisson arrivals and all at once. Every output equals the hierarchy
+    oracle's, and the server really coalesced requests."""
+    g, ix, H = quadtree8m
+    sizes = synth.request_sizes(600, first=3, hi=2_000_000)
+    reqs = [synth.request_points(g, 50_000 + r, n) for r, n in enumerate(sizes)]
+    say("server over quadtree8m: %d requests, %d points; oracle" % (len(reqs), int(sizes.sum())))
+    want = H.map(np.concatenate(reqs))
+    rng = np.random.default_rng(3)
+    cfg = bm.server_cfg(mem_budget_bytes=1 << 30, max_batch_points=1 << 22, max_slots=6, n_streams=4)
+    for name, arrivals in [("poisson", np.cumsum(rng.exponential(1e6 / 4000.0, len(reqs)))),
+                           ("all at once", np.zeros(len(reqs)))]:
+        say("server over quadtree8m:", name)
+        outs = [np.full(p.shape[0], -7, np.int32) for p in reqs]
+        srv = bm.Server(ix, cfg)
+        srv.run_trace(list(zip(reqs, outs)), arrivals)
+        st = srv.stats()
+        srv.close()
+        got = np.concatenate(outs)
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, (name, bad.size, bad[:5])
+        assert st["completed"] == len(reqs)
+        if name == "all at once":
+            assert st["mean_requests_per_batch"] > 2.0
