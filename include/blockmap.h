@@ -209,33 +209,53 @@ typedef struct {
   int64_t n;
 } bm_batch;
 
-/* Map nb batches with one persistent kernel. `batches` is a DEVICE array of
- * nb descriptors (the caller keeps it alive until the stream has passed this
- * call); their pointers must be valid device pointers for n points, and a
- * descriptor with n <= 0 is skipped. Work units of tuning->tile_points points
- * are taken from a device counter by the resident waves, so uneven batches
- * balance. Uses nb + 3 int64 of stream-ordered device scratch
- * (hipMallocAsync / hipFreeAsync on `stream`). Asynchronous. Batches must not
- * overlap each other's outputs.
- * Errors: BM_EINVAL (null index or table, nb < 0), BM_ENOMEM, BM_EHIP. */
-int bm_map_batches(const bm_index* index, const bm_batch* batches, int64_t nb, const bm_tuning* t,
-                   hipStream_t stream);
+/* Map nb batches that lie back to back in one array, with one persistent
+ * kernel: batch b is points [batch_off[b], batch_off[b+1]) of xy (device,
+ * interleaved (x, y) int32) and its results the same range of out_ids
+ * (device int32). batch_off is a DEVICE array of nb + 1 int64; a batch whose
+ * offsets decrease or start below 0 is skipped. The result equals one
+ * map_points call per batch, and so map_points over the concatenation. Work
+ * units of tuning->tile_points points are taken from a device counter by the
+ * resident waves, so uneven batches balance. Uses 32 * nb + 24 bytes of
+ * stream-ordered scratch (hipMallocAsync / hipFreeAsync on `stream`) for the
+ * descriptor table and the work-unit prefix. Asynchronous.
+ * Errors: BM_EINVAL (null pointer, nb < 0), BM_ENOMEM, BM_EHIP. */
+int bm_map_batches(const bm_index* index, const int32_t* xy, const int64_t* batch_off, int64_t nb,
+                   int32_t* out_ids, const bm_tuning* t, hipStream_t stream);
 
-/* The same as a captured HIP graph, for repeated use, with the batch table
- * given on the HOST (and checked there: n >= 0, non-null pointers when
- * n > 0): the plan owns a device batch table for up to max_batches batches
- * and a pinned staging copy; the
- * graph (table upload, work-unit prefix, persistent mapping kernel) is
- * captured once at creation and replayed by bm_batch_plan_run, which only
- * rewrites the staging table. A run waits for the previous run of the same
- * plan to finish before touching the staging table; different plans are
- * independent. */
+/* The same over batches anywhere in memory: `batches` is a DEVICE array of nb
+ * descriptors (the caller keeps it alive until the stream has passed this
+ * call); their pointers must be valid device pointers for n points, and a
+ * descriptor with n <= 0 is skipped. Batches must not overlap each other's
+ * outputs. Uses nb + 3 int64 of stream-ordered scratch.
+ * Errors: BM_EINVAL (null index or table, nb < 0), BM_ENOMEM, BM_EHIP. */
+int bm_map_batch_table(const bm_index* index, const bm_batch* batches, int64_t nb, const bm_tuning* t,
+                       hipStream_t stream);
+
+/* Both forms as captured HIP graphs, for repeated use. The plan owns a
+ * device descriptor table for up to max_batches batches, the work-unit
+ * prefix and pinned staging copies; two graphs are captured once at creation
+ * and replayed by the run calls, which only rewrite a staging copy:
+ *   bm_batch_plan_run: the offset form (xy, batch_off and out_ids as for
+ *     bm_map_batches; nb <= max_batches). The graph uploads a 32-byte header
+ *     (nb and the three pointers), writes the descriptor table on the device,
+ *     takes the prefix and runs the persistent kernel. A batch whose offsets
+ *     decrease, start below 0 or end beyond max_points is skipped, so a run
+ *     never touches xy or out_ids past max_points points.
+ *   bm_batch_plan_run_table: the descriptor form with the table given on the
+ *     HOST (checked there: n >= 0, non-null pointers when n > 0); the graph
+ *     uploads the whole table.
+ * A run waits for the previous run of the same plan to finish before
+ * touching the staging copies; different plans are independent.
+ * Errors: BM_EINVAL (null plan, nb outside [0, max_batches], bad
+ * descriptors, max_points < 0), BM_ENOMEM, BM_EHIP. */
 typedef struct bm_batch_plan bm_batch_plan;
 
-int bm_batch_plan_create(const bm_index* index, int64_t max_batches, const bm_tuning* t,
+int bm_batch_plan_create(const bm_index* index, int64_t max_points, int64_t max_batches, const bm_tuning* t,
                          bm_batch_plan** out);
-/* Errors: BM_EINVAL (nb > max_batches, bad descriptors), BM_EHIP. */
-int bm_batch_plan_run(bm_batch_plan* plan, const bm_batch* batches, int64_t nb, hipStream_t stream);
+int bm_batch_plan_run(bm_batch_plan* plan, const int32_t* xy, const int64_t* batch_off, int64_t nb,
+                      int32_t* out_ids, hipStream_t stream);
+int bm_batch_plan_run_table(bm_batch_plan* plan, const bm_batch* batches, int64_t nb, hipStream_t stream);
 void bm_batch_plan_destroy(bm_batch_plan* plan);
 
 /* ------------------------------------------------------------------------ */
@@ -258,7 +278,9 @@ enum {
 
 typedef struct {
   int64_t mem_budget_bytes;  /* device pool (and pinned host pool) for in-flight batches; each
-                                point in flight takes 12 bytes (+256-byte alignment per batch) */
+                                point in flight takes 12 bytes (+256-byte alignment per batch),
+                                and a batch of 2^20 points or more also its pre-sort scratch
+                                (about 12 bytes per point more) */
   int64_t max_batch_points;  /* points per device batch; larger requests are split */
   int32_t max_slots;         /* batches in flight at once (1..64) */
   int32_t n_streams;         /* streams the batches are spread over (1..16) */
@@ -272,7 +294,10 @@ typedef struct {
 int bm_server_cfg_default(bm_server_cfg* cfg);
 
 /* Allocates the pools, streams and two threads. The index must live on the
- * current device and outlive the server.
+ * current device and outlive the server. The server allocates nothing per
+ * batch: a batch's points, results and mapping scratch all come from the
+ * pool. After a device error it fails the queued requests and dispatches no
+ * more (submit then returns that error).
  * Errors: BM_EINVAL (budget below one full batch, fields out of range),
  * BM_ENOMEM, BM_EHIP. */
 int bm_server_create(const bm_index* index, const bm_server_cfg* cfg, bm_server** out);
@@ -284,8 +309,10 @@ int bm_server_create(const bm_index* index, const bm_server_cfg* cfg, bm_server*
  * error of an earlier device failure. */
 int bm_server_submit(bm_server* srv, const int32_t* xy, int64_t n, int32_t* out, uint64_t* ticket);
 
-/* Wait for a request (timeout_us < 0: no limit). BM_OK consumes the ticket;
- * BM_ETIMEDOUT leaves it pending; an unknown ticket gives BM_EINVAL. */
+/* Wait for a request (timeout_us < 0: no limit) until every piece of it has
+ * been retired, so no copy into its buffers is pending afterwards. BM_OK, or
+ * the error of a failed piece, consumes the ticket; BM_ETIMEDOUT leaves it
+ * pending; an unknown ticket gives BM_EINVAL. */
 int bm_server_wait(bm_server* srv, uint64_t ticket, int64_t timeout_us);
 
 typedef struct {
@@ -296,9 +323,11 @@ typedef struct {
   double mean_requests_per_batch;
   double p50_us, p99_us, mean_us, max_us;  /* submit-to-completion latency */
   double points_per_s;        /* points / (last completion - first submit) */
-} bm_server_stats;
+} bm_server_stats_t;
 
-int bm_server_get_stats(bm_server* srv, bm_server_stats* out);
+int bm_server_stats(bm_server* srv, bm_server_stats_t* out);
+/* The same (an earlier name). */
+int bm_server_get_stats(bm_server* srv, bm_server_stats_t* out);
 int bm_server_reset_stats(bm_server* srv);
 
 /* Load harness: submit reqs[i] at arrival_us[i] microseconds after the call

@@ -120,14 +120,17 @@ _SIGS = {
     "map_points_timed": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P, C.POINTER(LaunchTimes)]),
     "bm_tuning_default": (C.c_int, [C.POINTER(Tuning)]),
     "bm_autotune": (C.c_int, [_P, _P, _I64, C.POINTER(Tuning), _P]),
-    "bm_map_batches": (C.c_int, [_P, _P, _I64, C.POINTER(Tuning), _P]),
-    "bm_batch_plan_create": (C.c_int, [_P, _I64, C.POINTER(Tuning), C.POINTER(C.c_void_p)]),
-    "bm_batch_plan_run": (C.c_int, [_P, C.POINTER(Batch), _I64, _P]),
+    "bm_map_batches": (C.c_int, [_P, _P, _P, _I64, _P, C.POINTER(Tuning), _P]),
+    "bm_map_batch_table": (C.c_int, [_P, _P, _I64, C.POINTER(Tuning), _P]),
+    "bm_batch_plan_create": (C.c_int, [_P, _I64, _I64, C.POINTER(Tuning), C.POINTER(C.c_void_p)]),
+    "bm_batch_plan_run": (C.c_int, [_P, _P, _P, _I64, _P, _P]),
+    "bm_batch_plan_run_table": (C.c_int, [_P, C.POINTER(Batch), _I64, _P]),
     "bm_batch_plan_destroy": (None, [_P]),
     "bm_server_cfg_default": (C.c_int, [C.POINTER(ServerCfg)]),
     "bm_server_create": (C.c_int, [_P, C.POINTER(ServerCfg), C.POINTER(C.c_void_p)]),
     "bm_server_submit": (C.c_int, [_P, _P, _I64, _P, C.POINTER(C.c_uint64)]),
     "bm_server_wait": (C.c_int, [_P, C.c_uint64, _I64]),
+    "bm_server_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
     "bm_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
     "bm_server_reset_stats": (C.c_int, [_P]),
     "bm_server_run_trace": (C.c_int, [_P, C.POINTER(Request), _I64, _P]),
@@ -411,27 +414,56 @@ def batch_table(xys, outs, device=None):
     return torch.tensor(rows if rows else [[0, 0, 0]], dtype=torch.int64)[: len(rows)].to(dev)
 
 
-def map_batches(index: Index, table, stream=None, tuning: Tuning | None = None) -> None:
+def map_batch_table(index: Index, table, stream=None, tuning: Tuning | None = None) -> None:
     """Map every batch of a device table built by batch_table() in one launch."""
     import torch
     if not (isinstance(table, torch.Tensor) and table.is_cuda and table.dtype == torch.int64
             and table.dim() == 2 and table.shape[1] == 3 and table.is_contiguous()):
         raise TypeError("table must be a contiguous int64 CUDA tensor [nb, 3]")
     nb = table.shape[0]
-    _check(lib.bm_map_batches(index.handle, C.c_void_p(table.data_ptr()) if nb else None, nb,
-                              C.byref(tuning) if tuning is not None else None, _stream_handle(stream)))
+    _check(lib.bm_map_batch_table(index.handle, C.c_void_p(table.data_ptr()) if nb else None, nb,
+                                  C.byref(tuning) if tuning is not None else None, _stream_handle(stream)))
+
+
+def map_batches(index: Index, xy, batch_off, out, stream=None, tuning: Tuning | None = None) -> None:
+    """Map nb = len(batch_off) - 1 batches lying back to back in xy (int32
+    CUDA [n, 2]); batch_off is an int64 CUDA tensor of nb + 1 offsets, out an
+    int32 CUDA tensor [n]. One persistent launch."""
+    nb = batch_off.shape[0] - 1
+    if nb < 0:
+        raise ValueError("batch_off needs at least one entry")
+    if out.shape[0] != xy.shape[0]:
+        raise ValueError("out has the wrong length")
+    _check(lib.bm_map_batches(index.handle, _dev_ptr(xy, "int32", (2,)), _dev_ptr(batch_off, "int64"), nb,
+                              _dev_ptr(out, "int32"), C.byref(tuning) if tuning is not None else None,
+                              _stream_handle(stream)))
 
 
 class BatchPlan:
-    """Batched form as a captured HIP graph, replayed with a new host table."""
+    """Batched form as captured HIP graphs, replayed with new batches: offsets
+    into one concatenated array (run_offsets), or a host table of
+    descriptors (run, run_rows)."""
 
-    def __init__(self, index: Index, max_batches: int, tuning: Tuning | None = None):
+    def __init__(self, index: Index, max_batches: int, tuning: Tuning | None = None, max_points: int = 0):
         self._index = index  # keep alive
         h = C.c_void_p()
-        _check(lib.bm_batch_plan_create(index.handle, max_batches,
+        _check(lib.bm_batch_plan_create(index.handle, max_points, max_batches,
                                         C.byref(tuning) if tuning is not None else None, C.byref(h)))
         self._h = h
         self.max_batches = max_batches
+        self.max_points = max_points
+
+    def run_offsets(self, xy, batch_off, out, stream=None) -> None:
+        """Replay over batches back to back in xy (int32 CUDA [n, 2]) with
+        device offsets batch_off (int64 CUDA [nb + 1]) into out (int32 CUDA
+        [n]); batches ending beyond max_points are skipped."""
+        nb = batch_off.shape[0] - 1
+        if nb < 0:
+            raise ValueError("batch_off needs at least one entry")
+        if out.shape[0] != xy.shape[0]:
+            raise ValueError("out has the wrong length")
+        _check(lib.bm_batch_plan_run(self._h, _dev_ptr(xy, "int32", (2,)), _dev_ptr(batch_off, "int64"), nb,
+                                     _dev_ptr(out, "int32"), _stream_handle(stream)))
 
     def run(self, xys, outs, stream=None) -> None:
         rows = _batch_rows(xys, outs)
@@ -439,7 +471,7 @@ class BatchPlan:
 
     def run_rows(self, rows, nb: int, stream=None) -> None:
         """Replay with a prebuilt ctypes Batch array (see make_rows)."""
-        _check(lib.bm_batch_plan_run(self._h, rows, nb, _stream_handle(stream)))
+        _check(lib.bm_batch_plan_run_table(self._h, rows, nb, _stream_handle(stream)))
 
     def close(self) -> None:
         h, self._h = getattr(self, "_h", None), None
@@ -493,7 +525,7 @@ class Server:
 
     def stats(self) -> dict:
         st = ServerStats()
-        _check(lib.bm_server_get_stats(self._h, C.byref(st)))
+        _check(lib.bm_server_stats(self._h, C.byref(st)))
         return st.as_dict()
 
     def reset_stats(self) -> None:

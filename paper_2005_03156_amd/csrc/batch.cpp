@@ -1,6 +1,7 @@
-// Batched form: one persistent launch over a device table of point batches,
-// eager (bm_map_batches) or as a captured HIP graph (bm_batch_plan_*), and the
-// launch-shape autotuner.
+// Batched form: one persistent launch over a table of point batches, eager
+// (bm_map_batches over offsets into one concatenated array, bm_map_batch_table
+// over a device table of descriptors) or as captured HIP graphs
+// (bm_batch_plan_*: one per form), and the launch-shape autotuner.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -51,14 +52,17 @@ int current_is(const bm_index* ix, const char* who) {
 struct bm_batch_plan {
   const bm_index* index = nullptr;
   int64_t max_batches = 0;
+  int64_t max_points = 0;
   Tuning tuning{};
   size_t table_bytes = 0;
   char* d_table = nullptr;              // header + entries
+  OffsetHeader* d_off = nullptr;        // the offset form's header
   long long* d_meta = nullptr;          // [max_batches + 3]: nb, work counter, prefix
   char* h_staging = nullptr;            // pinned copy of the table
+  OffsetHeader* h_off = nullptr;        // pinned copy of the offset form's header
   hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph_off = nullptr;
+  hipGraphExec_t exec = nullptr, exec_off = nullptr;
   hipEvent_t done = nullptr;
   bool ran = false;
 };
@@ -67,35 +71,85 @@ static void plan_free(bm_batch_plan* p) {
   if (!p) return;
   if (p->done) (void)hipEventSynchronize(p->done);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->exec_off) (void)hipGraphExecDestroy(p->exec_off);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->graph_off) (void)hipGraphDestroy(p->graph_off);
   if (p->cap) (void)hipStreamDestroy(p->cap);
   if (p->done) (void)hipEventDestroy(p->done);
   if (p->d_table) (void)hipFree(p->d_table);
+  if (p->d_off) (void)hipFree(p->d_off);
   if (p->d_meta) (void)hipFree(p->d_meta);
   if (p->h_staging) (void)hipHostFree(p->h_staging);
+  if (p->h_off) (void)hipHostFree(p->h_off);
   delete p;
+}
+
+// Replays wait for the previous one to have read the staged table or header.
+static int plan_wait(bm_batch_plan* p, const char* who) {
+  if (!p->ran) return BM_OK;
+  const hipError_t e = hipEventSynchronize(p->done);
+  return e == hipSuccess ? BM_OK : hip_fail(e, std::string(who) + ": wait");
+}
+
+static int plan_launch(bm_batch_plan* p, hipGraphExec_t exec, hipStream_t stream, const char* who) {
+  hipError_t e = hipGraphLaunch(exec, stream);
+  if (e == hipSuccess) e = hipEventRecord(p->done, stream);
+  if (e != hipSuccess) return hip_fail(e, std::string(who) + ": launch");
+  p->ran = true;
+  return BM_OK;
 }
 
 extern "C" {
 
-__attribute__((visibility("default"))) int bm_map_batches(const bm_index* index, const bm_batch* batches,
-                                                         int64_t nb, const bm_tuning* t, hipStream_t stream) {
+__attribute__((visibility("default"))) int bm_map_batch_table(const bm_index* index, const bm_batch* batches,
+                                                             int64_t nb, const bm_tuning* t, hipStream_t stream) {
+  try {
+    const bm::TraceRange trace_range("bm_map_batch_table");
+    clear_error();
+    if (!index) return fail(BM_EINVAL, "bm_map_batch_table: null index");
+    if (nb < 0) return fail(BM_EINVAL, "bm_map_batch_table: nb < 0");
+    if (nb == 0) return BM_OK;
+    if (!batches) return fail(BM_EINVAL, "bm_map_batch_table: null batch table");
+    int rc = current_is(index, "bm_map_batch_table");
+    if (rc != BM_OK) return rc;
+    const Tuning tu = tuning_from(t);
+    void* meta = nullptr;
+    hipError_t e = hipMallocAsync(&meta, sizeof(long long) * (size_t)(nb + 3), stream);
+    if (e != hipSuccess) return hip_fail(e, "bm_map_batch_table: hipMallocAsync");
+    e = launch_batches(index->k, nullptr, nb, reinterpret_cast<const BatchEntry*>(batches),
+                       static_cast<long long*>(meta), tu, index->num_cu, stream);
+    hipError_t e2 = hipFreeAsync(meta, stream);
+    if (e != hipSuccess) return hip_fail(e, "bm_map_batch_table");
+    if (e2 != hipSuccess) return hip_fail(e2, "bm_map_batch_table: hipFreeAsync");
+    return BM_OK;
+  } catch (...) {
+    return fail(BM_EINVAL, "bm_map_batch_table: unexpected error");
+  }
+}
+
+__attribute__((visibility("default"))) int bm_map_batches(const bm_index* index, const int32_t* xy,
+                                                         const int64_t* batch_off, int64_t nb, int32_t* out_ids,
+                                                         const bm_tuning* t, hipStream_t stream) {
   try {
     const bm::TraceRange trace_range("bm_map_batches");
     clear_error();
     if (!index) return fail(BM_EINVAL, "bm_map_batches: null index");
     if (nb < 0) return fail(BM_EINVAL, "bm_map_batches: nb < 0");
     if (nb == 0) return BM_OK;
-    if (!batches) return fail(BM_EINVAL, "bm_map_batches: null batch table");
+    if (!xy || !batch_off || !out_ids) return fail(BM_EINVAL, "bm_map_batches: null pointer");
     int rc = current_is(index, "bm_map_batches");
     if (rc != BM_OK) return rc;
     const Tuning tu = tuning_from(t);
-    void* meta = nullptr;
-    hipError_t e = hipMallocAsync(&meta, sizeof(long long) * (size_t)(nb + 3), stream);
+    // scratch: the descriptor table, then the prefix kernel's meta
+    const size_t tab_bytes = (sizeof(BatchEntry) * (size_t)nb + 255) / 256 * 256;
+    void* scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, tab_bytes + sizeof(long long) * (size_t)(nb + 3), stream);
     if (e != hipSuccess) return hip_fail(e, "bm_map_batches: hipMallocAsync");
-    e = launch_batches(index->k, nullptr, nb, reinterpret_cast<const BatchEntry*>(batches),
-                       static_cast<long long*>(meta), tu, index->num_cu, stream);
-    hipError_t e2 = hipFreeAsync(meta, stream);
+    BatchEntry* tab = static_cast<BatchEntry*>(scratch);
+    long long* meta = reinterpret_cast<long long*>(static_cast<char*>(scratch) + tab_bytes);
+    e = launch_batch_offsets(nullptr, nb, xy, out_ids, batch_off, -1, nb, tab, index->num_cu, stream);
+    if (e == hipSuccess) e = launch_batches(index->k, nullptr, nb, tab, meta, tu, index->num_cu, stream);
+    hipError_t e2 = hipFreeAsync(scratch, stream);
     if (e != hipSuccess) return hip_fail(e, "bm_map_batches");
     if (e2 != hipSuccess) return hip_fail(e2, "bm_map_batches: hipFreeAsync");
     return BM_OK;
@@ -104,24 +158,29 @@ __attribute__((visibility("default"))) int bm_map_batches(const bm_index* index,
   }
 }
 
-__attribute__((visibility("default"))) int bm_batch_plan_create(const bm_index* index, int64_t max_batches,
-                                                               const bm_tuning* t, bm_batch_plan** out) {
+__attribute__((visibility("default"))) int bm_batch_plan_create(const bm_index* index, int64_t max_points,
+                                                               int64_t max_batches, const bm_tuning* t,
+                                                               bm_batch_plan** out) {
   try {
     clear_error();
     if (!index || !out) return fail(BM_EINVAL, "bm_batch_plan_create: null argument");
     *out = nullptr;
     if (max_batches < 1 || max_batches > (1 << 26)) return fail(BM_EINVAL, "bm_batch_plan_create: max_batches out of range");
+    if (max_points < 0) return fail(BM_EINVAL, "bm_batch_plan_create: max_points < 0");
     int rc = current_is(index, "bm_batch_plan_create");
     if (rc != BM_OK) return rc;
     bm_batch_plan* p = new (std::nothrow) bm_batch_plan();
     if (!p) return fail(BM_ENOMEM, "bm_batch_plan_create: out of host memory");
     p->index = index;
     p->max_batches = max_batches;
+    p->max_points = max_points;
     p->tuning = tuning_from(t);
     p->table_bytes = kHdrBytes + sizeof(BatchEntry) * (size_t)max_batches;
     hipError_t e = hipMalloc((void**)&p->d_table, p->table_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_off, sizeof(OffsetHeader));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_meta, sizeof(long long) * (size_t)(max_batches + 3));
     if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_staging, p->table_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_off, sizeof(OffsetHeader), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -129,18 +188,33 @@ __attribute__((visibility("default"))) int bm_batch_plan_create(const bm_index* 
       return hip_fail(e, "bm_batch_plan_create");
     }
     memset(p->h_staging, 0, p->table_bytes);
-    // capture: upload the staged table, prefix (also clears the counter), map
+    memset(p->h_off, 0, sizeof(OffsetHeader));
+    BatchEntry* tab = reinterpret_cast<BatchEntry*>(p->d_table + kHdrBytes);
+    // table form: upload the staged table, prefix (also clears the counter), map
     e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       hipError_t ec = hipMemcpyAsync(p->d_table, p->h_staging, p->table_bytes, hipMemcpyHostToDevice, p->cap);
       if (ec == hipSuccess)
-        ec = launch_batches(index->k, reinterpret_cast<const long long*>(p->d_table), 0,
-                            reinterpret_cast<const BatchEntry*>(p->d_table + kHdrBytes), p->d_meta, p->tuning,
+        ec = launch_batches(index->k, reinterpret_cast<const long long*>(p->d_table), 0, tab, p->d_meta, p->tuning,
                             index->num_cu, p->cap);
       e = hipStreamEndCapture(p->cap, &p->graph);
       if (ec != hipSuccess) e = ec;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    // offset form: upload the staged header, write the table on the device, prefix, map
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t ec = hipMemcpyAsync(p->d_off, p->h_off, sizeof(OffsetHeader), hipMemcpyHostToDevice, p->cap);
+      if (ec == hipSuccess)
+        ec = launch_batch_offsets(p->d_off, 0, nullptr, nullptr, nullptr, max_points, max_batches, tab,
+                                  index->num_cu, p->cap);
+      if (ec == hipSuccess)
+        ec = launch_batches(index->k, reinterpret_cast<const long long*>(p->d_off), 0, tab, p->d_meta, p->tuning,
+                            index->num_cu, p->cap);
+      e = hipStreamEndCapture(p->cap, &p->graph_off);
+      if (ec != hipSuccess) e = ec;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec_off, p->graph_off, nullptr, nullptr, 0);
     if (e != hipSuccess) {
       plan_free(p);
       return hip_fail(e, "bm_batch_plan_create: graph capture");
@@ -152,29 +226,41 @@ __attribute__((visibility("default"))) int bm_batch_plan_create(const bm_index* 
   }
 }
 
-__attribute__((visibility("default"))) int bm_batch_plan_run(bm_batch_plan* p, const bm_batch* batches, int64_t nb,
+__attribute__((visibility("default"))) int bm_batch_plan_run(bm_batch_plan* p, const int32_t* xy,
+                                                            const int64_t* batch_off, int64_t nb, int32_t* out_ids,
                                                             hipStream_t stream) {
   try {
     const bm::TraceRange trace_range("bm_batch_plan_run");
     clear_error();
     if (!p) return fail(BM_EINVAL, "bm_batch_plan_run: null plan");
-    if (nb > p->max_batches) return fail(BM_EINVAL, "bm_batch_plan_run: more batches than the plan holds");
-    int rc = check_batches(batches, nb, "bm_batch_plan_run");
+    if (nb < 0 || nb > p->max_batches) return fail(BM_EINVAL, "bm_batch_plan_run: nb outside [0, max_batches]");
+    if (nb > 0 && (!xy || !batch_off || !out_ids)) return fail(BM_EINVAL, "bm_batch_plan_run: null pointer");
+    int rc = current_is(p->index, "bm_batch_plan_run");
+    if (rc == BM_OK) rc = plan_wait(p, "bm_batch_plan_run");
     if (rc != BM_OK) return rc;
-    rc = current_is(p->index, "bm_batch_plan_run");
-    if (rc != BM_OK) return rc;
-    hipError_t e = hipSuccess;
-    if (p->ran) e = hipEventSynchronize(p->done);  // the previous replay has read the staging table
-    if (e != hipSuccess) return hip_fail(e, "bm_batch_plan_run: wait");
-    memcpy(p->h_staging, &nb, sizeof nb);
-    if (nb > 0) memcpy(p->h_staging + kHdrBytes, batches, sizeof(BatchEntry) * (size_t)nb);
-    e = hipGraphLaunch(p->exec, stream);
-    if (e == hipSuccess) e = hipEventRecord(p->done, stream);
-    if (e != hipSuccess) return hip_fail(e, "bm_batch_plan_run: launch");
-    p->ran = true;
-    return BM_OK;
+    *p->h_off = OffsetHeader{nb, xy, out_ids, reinterpret_cast<const long long*>(batch_off)};
+    return plan_launch(p, p->exec_off, stream, "bm_batch_plan_run");
   } catch (...) {
     return fail(BM_EINVAL, "bm_batch_plan_run: unexpected error");
+  }
+}
+
+__attribute__((visibility("default"))) int bm_batch_plan_run_table(bm_batch_plan* p, const bm_batch* batches,
+                                                                  int64_t nb, hipStream_t stream) {
+  try {
+    const bm::TraceRange trace_range("bm_batch_plan_run_table");
+    clear_error();
+    if (!p) return fail(BM_EINVAL, "bm_batch_plan_run_table: null plan");
+    if (nb > p->max_batches) return fail(BM_EINVAL, "bm_batch_plan_run_table: more batches than the plan holds");
+    int rc = check_batches(batches, nb, "bm_batch_plan_run_table");
+    if (rc == BM_OK) rc = current_is(p->index, "bm_batch_plan_run_table");
+    if (rc == BM_OK) rc = plan_wait(p, "bm_batch_plan_run_table");
+    if (rc != BM_OK) return rc;
+    memcpy(p->h_staging, &nb, sizeof nb);
+    if (nb > 0) memcpy(p->h_staging + kHdrBytes, batches, sizeof(BatchEntry) * (size_t)nb);
+    return plan_launch(p, p->exec, stream, "bm_batch_plan_run_table");
+  } catch (...) {
+    return fail(BM_EINVAL, "bm_batch_plan_run_table: unexpected error");
   }
 }
 

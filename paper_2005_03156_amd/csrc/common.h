@@ -111,6 +111,16 @@ struct BatchEntry {
   int64_t n;
 };
 
+// Header of an offset-form batched call as the graph form stages it in
+// device memory: batch b is points [off[b], off[b+1]) of xy, results into the
+// same range of out. nb comes first, where the prefix kernel reads it.
+struct OffsetHeader {
+  long long nb;
+  const int32_t* xy;
+  int32_t* out;
+  const long long* off;
+};
+
 // Calls of at least kPresortMin points are spatially sorted in chunks of
 // KIndex::presort_chunk points before mapping (when Tuning::presort is set),
 // up to kPresortSuper points (all their chunks) per round of sort passes. The
@@ -149,16 +159,30 @@ struct LaunchTimer {
 };
 
 // Launchers (map_kernels.hip). Return hipSuccess or the launch error.
+// launch_map takes its pre-sort scratch from stream-ordered memory, or, when
+// ws is given, from the ws_bytes there (never allocating; with less than
+// map_scratch_bytes it sorts fewer points per round, or none).
 hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
-                      const Tuning& t, int num_cu, hipStream_t stream, LaunchTimer* timer = nullptr);
+                      const Tuning& t, int num_cu, hipStream_t stream, LaunchTimer* timer = nullptr,
+                      void* ws = nullptr, size_t ws_bytes = 0);
+// Scratch bytes a call of n points uses at full speed (0 when it is not
+// pre-sorted).
+size_t map_scratch_bytes(const KIndex& ix, int64_t n, const Tuning& t);
+// Offset form of the batched call: writes the descriptor table of nb batches
+// (from hdr when given, else from the arguments) into tab; max_nb bounds nb
+// (the launch shape); max_points < 0: no bound on the offsets.
+hipError_t launch_batch_offsets(const OffsetHeader* hdr, long long nb, const int32_t* xy, int32_t* out,
+                                const int64_t* off, long long max_points, long long max_nb, BatchEntry* tab,
+                                int num_cu, hipStream_t stream);
 // Batched form: meta must hold nb + 3 int64 (nb, work counter, prefix).
 hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, const BatchEntry* tab,
                           long long* meta, const Tuning& t, int num_cu, hipStream_t stream);
 hipError_t launch_quantize(const double* lonlat, int64_t n, int32_t* xy, int num_cu,
                            hipStream_t stream);
-// Points per block into counts[0 .. nb] (the last slot: ids outside [0, nb)).
+// Per-point join: out[i] = table[ids[i]] for ids in [0, nb), else fill.
 hipError_t launch_join(const int32_t* ids, int64_t n, const int64_t* table, int32_t nb, int64_t fill, int64_t* out,
                        int num_cu, hipStream_t stream);
+// Points per block into counts[0 .. nb] (the last slot: ids outside [0, nb)).
 hipError_t launch_count(const int32_t* ids, int64_t n, int32_t nb, unsigned long long* counts, int num_cu,
                         hipStream_t stream);
 // Cover form: every point looked up in the cell trie; boundary cells resolved

@@ -644,6 +644,29 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(const long long* __r
   }
 }
 
+// Offset form of the batched call: batch b is points [off[b], off[b+1]) of
+// one concatenated xy array, its results the same range of out. The
+// descriptor table is written here, on the device: from the arguments, or,
+// when hdr is given, from the header the graph form stages (nb, xy, out, off).
+// A batch whose offsets decrease, start below 0 or end beyond max_points
+// (max_points < 0: no bound) gets n = 0 and is skipped.
+__global__ __launch_bounds__(256) void batch_offsets_kernel(const OffsetHeader* __restrict__ hdr,
+                                                            const long long nb_arg, const int32_t* xy_arg,
+                                                            int32_t* out_arg, const long long* off_arg,
+                                                            const long long max_points,
+                                                            BatchEntry* __restrict__ tab) {
+  const long long nb = hdr ? hdr->nb : nb_arg;
+  const int32_t* xy = hdr ? hdr->xy : xy_arg;
+  int32_t* out = hdr ? hdr->out : out_arg;
+  const long long* off = hdr ? hdr->off : off_arg;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+    const long long o0 = off[b], o1 = off[b + 1];
+    const bool ok = o0 >= 0 && o1 >= o0 && (max_points < 0 || o1 <= max_points);
+    tab[b] = BatchEntry{xy + 2 * (ok ? o0 : 0), out + (ok ? o0 : 0), ok ? o1 - o0 : 0};
+  }
+}
+
 template <int kChunkShift>
 __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map_kernel(const KIndex ix, const BatchEntry* __restrict__ tab,
                                                            long long* __restrict__ meta, const int unit) {
@@ -1301,8 +1324,37 @@ static void sort_passes(const int4 rb, const int2* p, const long long m, const l
                        dim3(Bins<kBB>::kRefThreads), 0, stream, sorted, perm, chunk, cursor, pstart, rb, shx, shy);
 }
 
+// Scratch of a pre-sorted call that sorts `super` points per round in chunks
+// of `chunk`: per chunk the sort's bin totals, cursors and piece starts, then
+// the sorted copy (int2) and the permutation (int) of `super` points.
+struct PresortPlan {
+  long long chunk = 0, super = 0, max_nc = 0;
+  size_t hist_bytes = 0, bytes = 0;
+};
+
+static PresortPlan presort_plan(long long chunk, long long super) {
+  PresortPlan pl;
+  pl.chunk = chunk;
+  pl.super = super;
+  pl.max_nc = (super + chunk - 1) / chunk;
+  pl.hist_bytes = (sizeof(unsigned) * (size_t)pl.max_nc * (2 * (size_t)kBins + kPStride) + 255) / 256 * 256;
+  pl.bytes = pl.hist_bytes + (size_t)super * (sizeof(int2) + sizeof(int)) + 256;
+  return pl;
+}
+
+static bool wants_presort(const KIndex& ix, int64_t n, const Tuning& t) {
+  return t.presort && n >= kPresortMin && ix.root_box.x < ix.root_box.y && ix.root_box.z < ix.root_box.w;
+}
+
+size_t map_scratch_bytes(const KIndex& ix, int64_t n, const Tuning& t) {
+  if (!wants_presort(ix, n, t)) return 0;
+  const long long super = std::min<long long>(n, kPresortSuper);
+  return presort_plan(std::min<long long>(super, ix.presort_chunk), super).bytes;
+}
+
 hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* out,
-                      const Tuning& t, int num_cu, hipStream_t stream, LaunchTimer* timer) {
+                      const Tuning& t, int num_cu, hipStream_t stream, LaunchTimer* timer, void* ws,
+                      size_t ws_bytes) {
   const int2* p = reinterpret_cast<const int2*>(xy);
   auto mark = [&](int slot) {
     if (timer && timer->n < LaunchTimer::kMax) {
@@ -1310,8 +1362,26 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
       timer->tag[timer->n++] = slot;
     }
   };
-  const bool presort = t.presort && n >= kPresortMin && ix.root_box.x < ix.root_box.y &&
-                       ix.root_box.z < ix.root_box.w;
+  bool presort = wants_presort(ix, n, t);
+  // Spatially sorted through scratch (12 bytes per point, up to kPresortSuper
+  // points at a time): every sort pass runs once over all chunks of a
+  // super-chunk (chunk = blockIdx.y), then one mapping launch per chunk keeps
+  // its scattered result stores within the chunk's window. The scratch is
+  // stream-ordered memory, or the caller's workspace: then the call sorts as
+  // many points per round as the workspace holds (in chunks no larger), and
+  // maps unsorted when it holds fewer than kPresortMin.
+  PresortPlan pl;
+  if (presort) {
+    long long super = std::min<long long>(n, kPresortSuper);
+    pl = presort_plan(std::min<long long>(super, ix.presort_chunk), super);
+    if (ws) {
+      while (pl.bytes > ws_bytes && super >= 2 * kPresortMin) {
+        super = super / 2;
+        pl = presort_plan(std::min<long long>(super, ix.presort_chunk), super);
+      }
+      presort = pl.bytes <= ws_bytes;
+    }
+  }
   if (!presort) {
     mark(0);
     switch (t.edge_chunk) {
@@ -1322,22 +1392,17 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
     mark(1);
     return hipGetLastError();
   }
-  // Spatially sorted through stream-ordered scratch (12 bytes per point, up
-  // to kPresortSuper points at a time): every sort pass runs once over all
-  // chunks of a super-chunk (chunk = blockIdx.y), then one mapping launch per
-  // chunk keeps its scattered result stores within the chunk's window.
-  const long long chunk = std::min<long long>(n, ix.presort_chunk);
-  const long long super = std::min<long long>(n, kPresortSuper);
-  const long long max_nc = (super + chunk - 1) / chunk;
-  const size_t hist_bytes = (sizeof(unsigned) * (size_t)max_nc * (2 * (size_t)kBins + kPStride) + 255) / 256 * 256;
-  const size_t bytes = hist_bytes + (size_t)super * (sizeof(int2) + sizeof(int)) + 256;
-  void* scratch = nullptr;
-  hipError_t e = hipMallocAsync(&scratch, bytes, stream);
-  if (e != hipSuccess) return e;
+  const long long chunk = pl.chunk, super = pl.super, max_nc = pl.max_nc;
+  void* scratch = ws;
+  hipError_t e = hipSuccess;
+  if (!ws) {
+    e = hipMallocAsync(&scratch, pl.bytes, stream);
+    if (e != hipSuccess) return e;
+  }
   unsigned* tot = static_cast<unsigned*>(scratch);
   unsigned* cursor = tot + max_nc * kBins;
   unsigned* pstart = cursor + max_nc * kBins;
-  int2* sorted = reinterpret_cast<int2*>(static_cast<char*>(scratch) + hist_bytes);
+  int2* sorted = reinterpret_cast<int2*>(static_cast<char*>(scratch) + pl.hist_bytes);
   int* perm = reinterpret_cast<int*>(sorted + super);
   hipLaunchKernelGGL(bin_zero_kernel, dim3((unsigned)std::min<long long>(max_nc * 4, 1024)), dim3(1024), 0, stream,
                      tot, max_nc * kBins);
@@ -1361,6 +1426,7 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
     }
     e = hipGetLastError();
   }
+  if (ws) return e;
   const hipError_t e2 = hipFreeAsync(scratch, stream);
   return e != hipSuccess ? e : e2;
 }
@@ -1371,6 +1437,15 @@ static void launch_batch_map(const KIndex& ix, const BatchEntry* tab, long long*
   const int per_cu = std::max(1, std::min(t.blocks_per_cu, resident_blocks<batch_map_kernel<kShift>>()));
   hipLaunchKernelGGL(batch_map_kernel<kShift>, dim3((unsigned)(num_cu * per_cu)), dim3(kBlock), 0, stream, ix, tab,
                      meta, t.tile_points);
+}
+
+hipError_t launch_batch_offsets(const OffsetHeader* hdr, long long nb, const int32_t* xy, int32_t* out,
+                                const int64_t* off, long long max_points, long long max_nb, BatchEntry* tab,
+                                int num_cu, hipStream_t stream) {
+  const long long blocks = std::max<long long>(1, std::min<long long>((max_nb + 255) / 256, (long long)num_cu * 4));
+  hipLaunchKernelGGL(batch_offsets_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, hdr, nb, xy, out,
+                     reinterpret_cast<const long long*>(off), max_points, tab);
+  return hipGetLastError();
 }
 
 hipError_t launch_batches(const KIndex& ix, const long long* hdr, long long nb, const BatchEntry* tab,

@@ -5,11 +5,16 @@
 // enough pool memory are free: the batch's points are packed contiguously into
 // a pinned host pool, copied to the same offsets of a device pool, mapped with
 // one plain kernel launch over the concatenation, and copied back, all on one
-// of several streams, so batches overlap on the device. A completion thread
-// retires batches in dispatch order, scatters results to the callers' buffers,
-// releases pool memory and slots, and records each request's latency.
+// of several streams, so batches overlap on the device. A batch's pool range
+// also holds the mapping call's pre-sort scratch, so the memory budget bounds
+// everything the server uses on the device. A completion thread retires
+// whichever in-flight batch has finished, scatters results to the callers'
+// buffers, releases pool memory and slots, and records each request's latency.
 // Requests larger than a batch are split into pieces; a request completes when
 // its last piece does. Results are those of map_points on each request alone.
+// After a device error the server fails every queued piece and dispatches no
+// more; a request's wait returns once all its pieces have been retired, so no
+// copy into its buffers is still pending.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -95,7 +100,7 @@ struct Batch {
   std::vector<Piece> pieces;
   std::vector<char> direct_out;  // per piece: result copied straight to the caller
   int64_t npts = 0;
-  int64_t off = 0, bytes = 0;  // pool range: xy then out
+  int64_t off = 0, bytes = 0;  // pool range: xy, out, then the mapping call's scratch
   int slot = -1;
   bool launched = false;
   int status = BM_OK;
@@ -153,17 +158,33 @@ struct bm_server {
 };
 
 void bm_server::dispatch_loop() {
-  if (hipSetDevice(device) != hipSuccess) {
-    std::lock_guard<std::mutex> g(mu);
+  const bool dev_ok = hipSetDevice(device) == hipSuccess;
+  std::unique_lock<std::mutex> lk(mu);
+  if (!dev_ok) {  // the loop below then fails every queued piece
     fatal = BM_EHIP;
     fatal_msg = "server: hipSetDevice failed";
-    return;
   }
-  std::unique_lock<std::mutex> lk(mu);
   uint64_t nbatch = 0;
   for (;;) {
-    cv_dispatch.wait(lk, [&] { return stop || (!queue.empty() && !free_slots.empty()); });
+    cv_dispatch.wait(lk, [&] { return stop || fatal != BM_OK || (!queue.empty() && !free_slots.empty()); });
     if (stop) break;
+    if (fatal != BM_OK) {
+      // a device error: fail what is queued, dispatch nothing more
+      const auto now = Clock::now();
+      while (!queue.empty()) {
+        Request* r = queue.front().r;
+        queue.pop_front();
+        r->status = fatal;
+        if (--r->pieces_left == 0) {
+          r->done = true;
+          completed++;
+          lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
+        }
+      }
+      cv_done.notify_all();
+      cv_dispatch.wait(lk, [&] { return stop || !queue.empty(); });
+      continue;
+    }
     // coalescing window: a small head batch may wait briefly for more arrivals
     if (cfg.coalesce_us > 0) {
       const auto deadline = queue.front().r->t_submit + std::chrono::microseconds(cfg.coalesce_us);
@@ -183,7 +204,8 @@ void bm_server::dispatch_loop() {
       b->npts += queue.front().n;
       queue.pop_front();
     }
-    b->bytes = align_up(8 * b->npts) + align_up(4 * b->npts);
+    const int64_t ws_bytes = align_up((int64_t)map_scratch_bytes(index->k, b->npts, tuning));
+    b->bytes = align_up(8 * b->npts) + align_up(4 * b->npts) + ws_bytes;
     int64_t off = alloc->alloc(b->bytes);
     if (off < 0) {
       // not enough free pool memory: put the pieces back (FIFO order kept) and
@@ -231,7 +253,8 @@ void bm_server::dispatch_loop() {
     flush_run(pos);
     if (e == hipSuccess)
       e = launch_map(index->k, reinterpret_cast<const int32_t*>(dx), b->npts,
-                     reinterpret_cast<int32_t*>(d_pool + out_off), tuning, index->num_cu, s);
+                     reinterpret_cast<int32_t*>(d_pool + out_off), tuning, index->num_cu, s, nullptr,
+                     ws_bytes ? d_pool + out_off + align_up(4 * b->npts) : nullptr, (size_t)ws_bytes);
     pos = 0;
     run0 = -1;
     auto flush_out = [&](int64_t end) {
@@ -254,6 +277,9 @@ void bm_server::dispatch_loop() {
     }
     flush_out(pos);
     if (e == hipSuccess) e = hipEventRecord(events[b->slot], s);
+    // after a failed enqueue, what was queued must finish before the batch's
+    // pool range and slot can be released
+    if (e != hipSuccess) (void)hipStreamSynchronize(s);
     bm::trace_pop();
 
     lk.lock();
@@ -356,8 +382,11 @@ __attribute__((visibility("default"))) int bm_server_create(const bm_index* inde
     if (c.max_batch_points < 64 || c.max_slots < 1 || c.max_slots > 64 || c.n_streams < 1 || c.n_streams > 16 ||
         c.queue_capacity < 1 || c.coalesce_us < 0)
       return fail(BM_EINVAL, "bm_server_create: configuration out of range");
-    if (c.mem_budget_bytes < align_up(8 * c.max_batch_points) + align_up(4 * c.max_batch_points))
-      return fail(BM_EINVAL, "bm_server_create: memory budget below one full batch (12 bytes per point)");
+    const int64_t full_batch = align_up(8 * c.max_batch_points) + align_up(4 * c.max_batch_points) +
+                               align_up((int64_t)map_scratch_bytes(index->k, c.max_batch_points, tuning_from(&c.tuning)));
+    if (c.mem_budget_bytes < full_batch)
+      return fail(BM_EINVAL, "bm_server_create: memory budget below one full batch (" + std::to_string(full_batch) +
+                                 " bytes: 12 per point, plus the pre-sort scratch of batches of 2^20 points or more)");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != index->device)
       return fail(BM_EINVAL, "bm_server_create: the index must live on the current device");
@@ -454,20 +483,19 @@ __attribute__((visibility("default"))) int bm_server_wait(bm_server* s, uint64_t
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return fail(BM_EINVAL, "bm_server_wait: unknown ticket");
   Request* r = it->second;
-  auto ready = [&] { return r->done || s->fatal != BM_OK; };
+  auto ready = [&] { return r->done; };  // every piece retired, failed ones too
   if (timeout_us < 0) {
     s->cv_done.wait(lk, ready);
   } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
     return fail(BM_ETIMEDOUT, "bm_server_wait: timed out");
   }
-  if (!r->done) return fail(s->fatal, s->fatal_msg);
   const int st = r->status;
   s->reqs.erase(it);
   delete r;
   return st == BM_OK ? BM_OK : fail(st, "bm_server_wait: the request failed on the device");
 }
 
-__attribute__((visibility("default"))) int bm_server_get_stats(bm_server* s, bm_server_stats* o) {
+__attribute__((visibility("default"))) int bm_server_get_stats(bm_server* s, bm_server_stats_t* o) {
   if (!s || !o) return fail(BM_EINVAL, "bm_server_get_stats: null argument");
   std::vector<double> v;
   {
@@ -496,6 +524,10 @@ __attribute__((visibility("default"))) int bm_server_get_stats(bm_server* s, bm_
   for (double x : v) sum += x;
   o->mean_us = v.empty() ? 0.0 : sum / (double)v.size();
   return BM_OK;
+}
+
+__attribute__((visibility("default"))) int bm_server_stats(bm_server* s, bm_server_stats_t* o) {
+  return bm_server_get_stats(s, o);
 }
 
 __attribute__((visibility("default"))) int bm_server_reset_stats(bm_server* s) {

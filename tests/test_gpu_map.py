@@ -526,43 +526,47 @@ def _cluster_batches(g, sizes, seed):
 
 def test_batched_equals_oracle_and_plain(torch_cuda, bm, grid221k):
     """Batches of 0 to 200k points in one persistent launch, for three tile
-    sizes: every output equals the hierarchy oracle's, and the plain path's
-    per-batch result."""
+    sizes, through both batched calls (offsets into one concatenated array,
+    and a device table of descriptors): every output equals the hierarchy
+    oracle's, and the plain path's per-batch result."""
     torch = torch_cuda
     g, ix, H = grid221k
     sizes = synth.sizes(synth.key("batches10k", 2, 0), 300, 0, 0, 0, 200_000)
     sizes[:5] = [0, 1, 63, 64, 65]
     say("batched: %d batches, %d points" % (len(sizes), sizes.sum()))
-    pts = _cluster_batches(g, sizes, 1)
-    want = H.map(np.concatenate(pts))
-    xys = [torch.from_numpy(p).cuda() for p in pts]
-    plain = torch.cat([bm.map_points(ix, xy) for xy in xys]).cpu().numpy()
+    allp, off = synth.batch_points(g, np.asarray(sizes), first=100000)
+    want = H.map(allp)
+    xy = torch.from_numpy(allp).cuda()
+    doff = torch.from_numpy(off).cuda()
+    xys = [xy[off[b]:off[b + 1]] for b in range(len(sizes))]
+    plain = torch.cat([bm.map_points(ix, x) for x in xys]).cpu().numpy()
     assert np.array_equal(plain, want)
     for tile in (64, 1024, 8192):
-        outs = [torch.full((p.shape[0],), -7, dtype=torch.int32, device="cuda") for p in pts]
-        tab = bm.batch_table(xys, outs)
-        bm.map_batches(ix, tab, tuning=bm.Tuning(8, 4, tile))
+        out = torch.full((allp.shape[0],), -7, dtype=torch.int32, device="cuda")
+        bm.map_batches(ix, xy, doff, out, tuning=bm.Tuning(8, 4, tile))
+        outs = [torch.full((x.shape[0],), -7, dtype=torch.int32, device="cuda") for x in xys]
+        bm.map_batch_table(ix, bm.batch_table(xys, outs), tuning=bm.Tuning(8, 4, tile))
         torch.cuda.synchronize()
-        got = torch.cat(outs).cpu().numpy()
-        bad = np.flatnonzero(got != want)
-        assert bad.size == 0, (tile, bad.size, bad[:5])
+        for name, got in (("offsets", out.cpu().numpy()), ("table", torch.cat(outs).cpu().numpy())):
+            bad = np.flatnonzero(got != want)
+            assert bad.size == 0, (name, tile, bad.size, bad[:5])
 
 
 def test_batched_full_size_every_point(torch_cuda, bm, grid221k):
     """The batched workload at full size (10,000 batches of 1 to 1M points,
-    729M points over the census-scale index), through the captured graph as
-    the benchmark replays it: every output equals the hierarchy oracle's."""
+    729M points over the census-scale index), through the captured graph of
+    the offset form as the benchmark replays it: every output equals the
+    hierarchy oracle's."""
     torch = torch_cuda
     g, ix, H = grid221k
     sizes = synth.batch_sizes()
     say("batched full size: generating", int(sizes.sum()), "points")
     host, off = synth.batch_points(g, sizes)
     xy = torch.from_numpy(host).cuda()
+    doff = torch.from_numpy(off).cuda()
     out = torch.full((host.shape[0],), -7, dtype=torch.int32, device="cuda")
-    rows = [(xy.data_ptr() + 8 * int(off[b]), out.data_ptr() + 4 * int(off[b]), int(sizes[b]))
-            for b in range(len(sizes))]
-    plan = bm.BatchPlan(ix, len(sizes), bm.Tuning(4, 8, 512))
-    plan.run_rows(bm.make_rows(rows), len(sizes), torch.cuda.current_stream())
+    plan = bm.BatchPlan(ix, len(sizes), bm.Tuning(4, 8, 512), max_points=host.shape[0])
+    plan.run_offsets(xy, doff, out)
     torch.cuda.synchronize()
     plan.close()
     got = out.cpu().numpy()
@@ -574,11 +578,13 @@ def test_batched_full_size_every_point(torch_cuda, bm, grid221k):
 
 
 def test_batch_plan_graph_replays(torch_cuda, bm, grid221k):
-    """Captured graph replayed with different tables; eager work and syncs in
-    between; every replay equals the plain result."""
+    """Both captured graphs replayed with different batches, eager work and
+    syncs in between: every replay equals the plain result. The offset form
+    skips batches whose offsets decrease or end beyond max_points, leaving
+    their outputs untouched."""
     torch = torch_cuda
     g, ix, H = grid221k
-    plan = bm.BatchPlan(ix, 64, bm.Tuning(8, 4, 512))
+    plan = bm.BatchPlan(ix, 64, bm.Tuning(8, 4, 512), max_points=1_000_000)
     for rep in range(4):
         sizes = synth.sizes(synth.key("batches10k", 2, 10 + rep), 10 + 13 * rep, 0, 0, 0, 50_000)
         say("plan replay", rep, len(sizes), sizes.sum())
@@ -589,7 +595,27 @@ def test_batch_plan_graph_replays(torch_cuda, bm, grid221k):
         torch.cuda.synchronize()
         for xy, o in zip(xys, outs):
             assert torch.equal(bm.map_points(ix, xy), o), rep
+        allp = np.concatenate(pts)
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        xy = torch.from_numpy(allp).cuda()
+        out = torch.full((allp.shape[0],), -7, dtype=torch.int32, device="cuda")
+        plan.run_offsets(xy, torch.from_numpy(off).cuda(), out)
         torch.cuda.synchronize()
+        assert torch.equal(bm.map_points(ix, xy), out), rep
+    # guarded offsets: batch 1 decreases, batch 3 ends beyond max_points
+    pts = synth.points("grid221k", 300_000, i0=70_000_000)
+    xy = torch.from_numpy(pts).cuda()
+    off = torch.tensor([0, 1000, 900, 5000, 300_000], dtype=torch.int64, device="cuda")
+    small = bm.BatchPlan(ix, 8, bm.Tuning(8, 4, 512), max_points=200_000)
+    out = torch.full((300_000,), -7, dtype=torch.int32, device="cuda")
+    small.run_offsets(xy, off, out)
+    torch.cuda.synchronize()
+    ref = bm.map_points(ix, xy)
+    torch.cuda.synchronize()
+    assert torch.equal(out[:900], ref[:900]) and (out[900:1000] == ref[900:1000]).all()
+    assert torch.equal(out[900:5000], ref[900:5000])
+    assert (out[5000:] == -7).all()
+    small.close()
     with pytest.raises(bm.BlockmapError):
         plan.run([xys[0]] * 65, [outs[0]] * 65)
     plan.close()
@@ -721,3 +747,29 @@ def test_server_over_quadtree8m_every_point(torch_cuda, bm, quadtree8m):
         assert st["completed"] == len(reqs)
         if name == "all at once":
             assert st["mean_requests_per_batch"] > 2.0
+
+
+def test_server_budget_covers_presort_scratch(torch_cuda, bm, grid221k):
+    """Batches of 2^20 points or more are pre-sorted, and their sort scratch
+    comes out of the server's memory budget: a budget of 12 bytes per point
+    alone is refused; one that also holds the scratch serves requests of 2^21
+    points (pre-sorted in the pool) with the ids each gets alone."""
+    torch = torch_cuda
+    g, ix, H = grid221k
+    mb = 1 << 21
+    with pytest.raises(bm.BlockmapError) as e:
+        bm.Server(ix, bm.server_cfg(mem_budget_bytes=12 * mb + 4096, max_batch_points=mb))
+    assert e.value.code == bm.BM_EINVAL and "scratch" in str(e.value)
+    sizes = [mb - 5, 1000, mb, 70_000, mb - 64]
+    reqs = [synth.points("grid221k", n, i0=90_000_000 + 3_000_000 * k) for k, n in enumerate(sizes)]
+    alone = [gpu_map(bm, torch, ix, p) for p in reqs]
+    srv = bm.Server(ix, bm.server_cfg(mem_budget_bytes=25 * mb, max_batch_points=mb, max_slots=4, n_streams=2))
+    outs = [np.full(p.shape[0], -7, np.int32) for p in reqs]
+    say("server, pre-sort scratch in the budget")
+    tickets = [srv.submit(p, o) for p, o in zip(reqs, outs)]
+    for t in tickets:
+        srv.wait(t)
+    srv.close()
+    for a, o in zip(alone, outs):
+        assert (a == o).all()
+    assert (np.concatenate(outs) == H.map(np.concatenate(reqs))).all()
