@@ -183,6 +183,20 @@ typedef struct {
 /* Fill *t with the defaults used when a tuning pointer is null. */
 int bm_tuning_default(bm_tuning* t);
 
+/* map_points without allocating, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no hipMalloc, hipFree or other allocation. Same
+ * arguments and results as map_points; n may be at most 2^22 (4,194,304)
+ * points, else BM_ERANGE. A call of 2^20 points or more is pre-sorted through
+ * a fixed 49 MiB array of device memory that every device the library runs
+ * on holds until the process ends; the array is shared by all calls on a
+ * device and keeps the last call's contents (each call clears what it needs
+ * cleared). Calls that overlap on one device (other streams, other threads)
+ * race on it: order them on one stream, or use map_points.
+ * Errors: BM_EINVAL (as map_points), BM_ERANGE (n > 2^22), BM_EHIP. */
+int map_points_noalloc(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
+                       hipStream_t stream);
+
 /* As map_points, with an explicit launch shape (t may be null). */
 int map_points_tuned(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,
                      const bm_tuning* t, hipStream_t stream);

@@ -116,6 +116,7 @@ _SIGS = {
     "bm_index_build_file": (C.c_int, [C.POINTER(IndexDesc), C.c_char_p]),
     "map_points": (C.c_int, [_P, _P, _I64, _P, _P]),
     "map_points_tuned": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P]),
+    "map_points_noalloc": (C.c_int, [_P, _P, _I64, _P, _P]),
     "bm_quantize_lonlat": (C.c_int, [_P, _I64, _P, _P]),
     "map_points_timed": (C.c_int, [_P, _P, _I64, _P, C.POINTER(Tuning), _P, C.POINTER(LaunchTimes)]),
     "bm_tuning_default": (C.c_int, [C.POINTER(Tuning)]),
@@ -265,6 +266,18 @@ def map_points(index: Index, xy, out=None, stream=None, tuning: Tuning | None = 
         _check(lib.map_points(index.handle, pxy, n, pout, s))
     else:
         _check(lib.map_points_tuned(index.handle, pxy, n, pout, C.byref(tuning), s))
+    return out
+
+
+def map_points_noalloc(index: Index, xy, out, stream=None):
+    """map_points through the entry point that allocates nothing (at most
+    2^22 points per call; out is a caller-allocated int32 CUDA tensor [n])."""
+    n = xy.shape[0]
+    pxy = _dev_ptr(xy, "int32", (2,))
+    pout = _dev_ptr(out, "int32")
+    if out.shape[0] != n:
+        raise ValueError("out has the wrong length")
+    _check(lib.map_points_noalloc(index.handle, pxy, n, pout, _stream_handle(stream)))
     return out
 
 
