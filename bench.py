@@ -694,7 +694,18 @@ def cpu_baseline(g, pts):
     method's work on the first 2M points, over the hierarchy the index
     filters (regions, counties, blocks: the tract level merged into counties,
     as the paper's own state / county / block) and over all four levels."""
+    import tempfile
+
     import oracle
+    # the oracle's source built for this host's CPU (-O3 -march=native), in a
+    # temporary directory; the in-tree copy is built for any x86-64 host
+    flags = "gcc -O3 -march=native, OpenMP"
+    tmpdir = tempfile.mkdtemp(prefix="bm_oracle_")
+    try:
+        oracle.use(oracle.build_native(tmpdir))
+    except Exception as e:  # no compiler on this host: the portable build
+        log("cpu baseline: native build failed (%s); timing the portable build" % e)
+        flags = "gcc -O3 (portable x86-64), OpenMP"
     H = oracle.Hier.from_geometry(g)
     sample = pts[:2_000_000]
     _, c4 = H.map(sample, with_counts=True)
@@ -725,8 +736,8 @@ def cpu_baseline(g, pts):
     single = n / (time.perf_counter() - t1)
     oracle.set_threads(cores)
     return {"value": passes * pts.shape[0] / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
-            "sample": "%d full passes over the workload's %d points (%.1f s), hierarchy route, C + OpenMP, gcc -O3"
-                      % (passes, pts.shape[0], dt),
+            "sample": "%d full passes over the workload's %d points (%.1f s), hierarchy route, C, %s"
+                      % (passes, pts.shape[0], dt, flags),
             "single_thread_points_per_s": single, "host": host_cpus(), "work_per_point": work}
 
 

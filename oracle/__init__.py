@@ -22,14 +22,37 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 
+FLAGS = ["-O3", "-std=gnu11", "-fopenmp", "-fPIC", "-shared"]
+
+
 def build(force: bool = False) -> str:
+    """The in-tree library, built for any x86-64 host (it travels with the
+    tree to other machines)."""
     src = os.path.join(_HERE, "oracle.c")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O3", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", src,
-                               "-o", tmp])
+        subprocess.check_call(["gcc"] + FLAGS + [src, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_native(directory: str) -> str:
+    """The same source built for the CPU it is built on (-march=native), into
+    `directory` (outside the tree: the result only runs on this machine's CPU
+    model). Returns the library path; use() switches to it."""
+    src = os.path.join(_HERE, "oracle.c")
+    path = os.path.join(directory, "liboracle_native.so")
+    subprocess.check_call(["gcc"] + FLAGS + ["-march=native", src, "-o", path])
+    return path
+
+
+def use(path: str) -> None:
+    """Load the oracle from `path` for every later call (objects made before
+    keep working only while the earlier library stays loaded)."""
+    global _LIB_PATH, _lib
+    _LIB_PATH = path
+    _lib = None
+    _L()
 
 
 class Counts(C.Structure):
@@ -147,7 +170,8 @@ class Hier:
         self._par = [_c(p, np.int32) for p in parents]
         arr = (C.c_void_p * max(len(self._par), 1))(*[p.ctypes.data for p in self._par])
         self._arr = arr
-        self._h = _L().orc_hier_create(self._vo.shape[0] - 1, _p(self._vo), _p(self._vv),
+        self._lib = _L()  # the library that made it also maps and frees it
+        self._h = self._lib.orc_hier_create(self._vo.shape[0] - 1, _p(self._vo), _p(self._vv),
                                        len(self._par), _p(self._ng) if len(self._ng) else None, arr)
 
     @classmethod
@@ -158,10 +182,11 @@ class Hier:
         pts = _c(xy, np.int32)
         out = np.empty(pts.shape[0], np.int32)
         cnt = Counts()
-        _L().orc_hier_map(self._h, pts.shape[0], _p(pts), _p(out), C.byref(cnt))
+        self._lib.orc_hier_map(self._h, pts.shape[0], _p(pts), _p(out), C.byref(cnt))
         return (out, cnt.as_dict()) if with_counts else out
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
-        if h and _lib is not None:
-            _lib.orc_hier_destroy(h)
+        lib = getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.orc_hier_destroy(h)
