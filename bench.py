@@ -43,10 +43,9 @@ PEAK_HBM_GBS = 8000.0
 # the workload's own points, taken in the CPU leg.
 COST = {"bbox_tests": 5, "edge_tests": 7, "x_ambiguous": 12}
 # Algorithmic HBM bytes per point: 8 in + 4 out for a call; the sorted mapping
-# kernel reads the sorted point and its permutation entry and writes the
-# result (8 + 4 + 4).
+# kernel reads the sorted point and writes its result in sorted order (8 + 4).
 BYTES_PER_POINT = 12.0
-SORTED_KERNEL_BYTES_PER_POINT = 16.0
+SORTED_KERNEL_BYTES_PER_POINT = 12.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2005_03156_amd", "csrc", "map_kernels.hip")
 LEGS = ["plain", "grid1k", "all-levels", "cover", "aggregate", "quantize", "batched", "served", "quadtree8m",
         "quadtree8m-kernel"]
@@ -94,14 +93,15 @@ def timed_calls(torch, fn, reps, stream):
 def launch_times(bm, ix, xy, out, stream, reps=3):
     """Mapping-kernel launches and sort phases of map_points, timed with HIP
     events on the stream they run on."""
-    tm = {"map_ms": 0.0, "sort_ms": 0.0, "map_launches": 0, "sort_launches": 0}
+    tm = {"map_ms": 0.0, "sort_ms": 0.0, "unsort_ms": 0.0, "map_launches": 0, "sort_launches": 0}
     for _ in range(reps):
         r = bm.map_points_timed(ix, xy, out, stream)
         for k in tm:
             tm[k] += r[k]
     launches = max(1, tm["map_launches"] // reps)
     return {"kernel_ms": tm["map_ms"] / reps / launches, "launches_per_call": launches,
-            "sort_ms_per_call": tm["sort_ms"] / reps, "kernel": "map_sorted_kernel" if tm["sort_launches"] else "map_kernel"}
+            "sort_ms_per_call": tm["sort_ms"] / reps, "unsort_ms_per_call": tm["unsort_ms"] / reps,
+            "kernel": "map_sorted_kernel" if tm["sort_launches"] else "map_kernel"}
 
 
 def copy_calibration(torch):
@@ -251,8 +251,9 @@ def headline(bm, torch, args):
     pts_per_launch = n / lt["launches_per_call"]
     bpp = read_traffic("map_sorted_kernel_grid221k_100m")
     traffic = bpp * pts_per_launch if bpp is not None else None
-    log("dominant kernel: %d launches/step, %.3f ms each (%.0f points), sort phases %.3f ms/step" % (
-        lt["launches_per_call"], lt["kernel_ms"], pts_per_launch, lt["sort_ms_per_call"]))
+    log("dominant kernel: %d launch(es)/step, %.3f ms each (%.0f points), sort passes %.3f ms/step, unsort "
+        "passes %.3f ms/step" % (lt["launches_per_call"], lt["kernel_ms"], pts_per_launch, lt["sort_ms_per_call"],
+                                  lt["unsort_ms_per_call"]))
     hbm_gbs = BYTES_PER_POINT * n / (step_ms * 1e-3) / 1e9
     res = {
         "metric": "points mapped/sec on 1 GPU, served/batched vs plain kernel; p50/p99 latency",
@@ -277,7 +278,7 @@ def headline(bm, torch, args):
                      "traffic": traffic,
                      "kernel": lt["kernel"], "kernel_ms": lt["kernel_ms"],
                      "launches_per_step": lt["launches_per_call"], "points_per_launch": pts_per_launch,
-                     "sort_ms_per_step": lt["sort_ms_per_call"],
+                     "sort_ms_per_step": lt["sort_ms_per_call"], "unsort_ms_per_step": lt["unsort_ms_per_call"],
                      "ops_basis": "method-equivalent integer lane-ops: the oracle's counts of the paper's "
                                   "work on this workload's points (box tests per level, ring-edge tests, "
                                   "exact cross products) over the hierarchy the index filters (regions, "
@@ -601,10 +602,11 @@ def profile_quadtree8m(bm, torch, g, ix, steps):
     lt = launch_times(bm, ix, xy, out, s, reps=steps)
     res = {"workload": "8M-block graded quadtree mesh, one resident 2^26-point chunk", "points": CH,
            "calls": steps, "map_launches_per_call": lt["launches_per_call"], "map_kernel_ms": lt["kernel_ms"],
-           "sort_ms_per_call": lt["sort_ms_per_call"],
-           "points_per_s_per_call": CH / ((lt["kernel_ms"] * lt["launches_per_call"] + lt["sort_ms_per_call"]) * 1e-3)}
-    log("quadtree8m chunk: %d mapping launch(es) of %.3f ms, sort %.3f ms per call" % (
-        lt["launches_per_call"], lt["kernel_ms"], lt["sort_ms_per_call"]))
+           "sort_ms_per_call": lt["sort_ms_per_call"], "unsort_ms_per_call": lt["unsort_ms_per_call"],
+           "points_per_s_per_call": CH / ((lt["kernel_ms"] * lt["launches_per_call"] + lt["sort_ms_per_call"] +
+                                           lt["unsort_ms_per_call"]) * 1e-3)}
+    log("quadtree8m chunk: %d mapping launch(es) of %.3f ms, sort %.3f ms, unsort %.3f ms per call" % (
+        lt["launches_per_call"], lt["kernel_ms"], lt["sort_ms_per_call"], lt["unsort_ms_per_call"]))
     return res
 
 
@@ -670,6 +672,7 @@ def bench_quadtree8m(bm, torch, g, ix):
     res = {"blocks": g.n_blocks, "vertices": int(g.verts.shape[0]), "points": N, "chunk": CH,
            "kernel_points_per_s": CH / (kern_ms * 1e-3), "kernel_ms_per_chunk": kern_ms,
            "map_kernel_ms": lt["kernel_ms"], "sort_ms_per_chunk": lt["sort_ms_per_call"],
+           "unsort_ms_per_chunk": lt["unsort_ms_per_call"],
            "end_to_end_points_per_s": N / t_wall, "end_to_end_first_chunk_identical": same,
            "index_device_bytes": info["device_bytes"],
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

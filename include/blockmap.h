@@ -172,10 +172,11 @@ typedef struct {
   int32_t presort;          /* 1: a call of at least 2^20 points is first sorted along a Z-curve
                                (Morton bins over the index, refined by Morton sub-cells: a
                                1024 x 1024 grid, or 4096 x 4096 for an index over 256 MB) in
-                               chunks of 2^22 points (2^26 for an index over 256 MB), so that
-                               nearby points are mapped together; it uses
-                               12 bytes of stream-ordered device scratch (hipMallocAsync) per
-                               point, for at most 2^27 points at a time (1.6 GB). 0: off */
+                               chunks of 2^24 points (2^26 for an index over 256 MB), so that
+                               nearby points are mapped together, and the results, computed in
+                               sorted order, are put back in the points' order; it uses
+                               20 bytes of stream-ordered device scratch (hipMallocAsync) per
+                               point, for at most 2^27 points at a time (2.7 GB). 0: off */
 } bm_tuning;
 
 /* Out-of-range fields are replaced by their defaults. */
@@ -188,7 +189,7 @@ int bm_tuning_default(bm_tuning* t);
  * forbid hipMalloc): no hipMalloc, hipFree or other allocation. Same
  * arguments and results as map_points; n may be at most 2^22 (4,194,304)
  * points, else BM_ERANGE. A call of 2^20 points or more is pre-sorted through
- * a fixed 49 MiB array of device memory that every device the library runs
+ * a fixed 81 MiB array of device memory that every device the library runs
  * on holds until the process ends; the array is shared by all calls on a
  * device and keeps the last call's contents (each call clears what it needs
  * cleared). Calls that overlap on one device (other streams, other threads)
@@ -294,7 +295,7 @@ typedef struct {
   int64_t mem_budget_bytes;  /* device pool (and pinned host pool) for in-flight batches; each
                                 point in flight takes 12 bytes (+256-byte alignment per batch),
                                 and a batch of 2^20 points or more also its pre-sort scratch
-                                (about 12 bytes per point more) */
+                                (about 20 bytes per point more) */
   int64_t max_batch_points;  /* points per device batch; larger requests are split */
   int32_t max_slots;         /* batches in flight at once (1..64) */
   int32_t n_streams;         /* streams the batches are spread over (1..16) */
@@ -360,13 +361,17 @@ int bm_server_run_trace(bm_server* srv, const bm_request* reqs, int64_t nreq, co
 void bm_server_destroy(bm_server* srv);
 
 /* Measurement aid: as map_points_tuned, but with HIP events recorded on
- * `stream` around each launch of the mapping kernel and each spatial-sort
- * phase; waits for the stream and returns the summed durations. */
+ * `stream` around each launch of the mapping kernel and each phase of the
+ * spatial pre-sort (the sort passes before a mapping launch, and the passes
+ * after it that put the results, computed in sorted order, back in the
+ * points' order); waits for the stream and returns the summed durations. */
 typedef struct {
   double map_ms;          /* mapping-kernel launches */
-  double sort_ms;         /* spatial pre-sort phases (0 when not sorted) */
+  double sort_ms;         /* sort passes (0 when not sorted) */
   int32_t map_launches;
-  int32_t sort_launches;
+  int32_t sort_launches;  /* rounds of sort passes */
+  double unsort_ms;       /* passes that put the results in the points' order */
+  int32_t unsort_launches;
 } bm_launch_times;
 
 int map_points_timed(const bm_index* index, const int32_t* xy, int64_t n, int32_t* out_ids,

@@ -71,7 +71,7 @@ class CoverInfo(C.Structure):
 
 class LaunchTimes(C.Structure):
     _fields_ = [("map_ms", C.c_double), ("sort_ms", C.c_double), ("map_launches", C.c_int32),
-                ("sort_launches", C.c_int32)]
+                ("sort_launches", C.c_int32), ("unsort_ms", C.c_double), ("unsort_launches", C.c_int32)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))

@@ -254,13 +254,14 @@ __attribute__((visibility("default"))) int map_points_timed(const bm_index* inde
     for (; made < LaunchTimer::kMax && e == hipSuccess; ++made) e = hipEventCreate(&tm->ev[made]);
     if (e == hipSuccess && n > 0) e = launch_map(index->k, xy, n, out_ids, tuning_from(t), index->num_cu, stream, tm);
     if (e == hipSuccess && tm->n > 0) e = hipEventSynchronize(tm->ev[tm->n - 1]);
-    double map_ms = 0, sort_ms = 0;
-    int maps = 0, sorts = 0;
+    double map_ms = 0, sort_ms = 0, unsort_ms = 0;
+    int maps = 0, sorts = 0, unsorts = 0;
     for (int i = 0; e == hipSuccess && i + 1 < tm->n; ++i) {
       float ms = 0;
       e = hipEventElapsedTime(&ms, tm->ev[i], tm->ev[i + 1]);
       if (tm->tag[i] == 0 && tm->tag[i + 1] == 1) { map_ms += ms; ++maps; }
-      if (tm->tag[i] == 2 && tm->tag[i + 1] == 0) { sort_ms += ms; ++sorts; }
+      if (tm->tag[i] == 2) { sort_ms += ms; ++sorts; }
+      if (tm->tag[i] == 3) { unsort_ms += ms; ++unsorts; }
     }
     for (int i = 0; i < made; ++i) (void)hipEventDestroy(tm->ev[i]);
     delete tm;
@@ -269,6 +270,8 @@ __attribute__((visibility("default"))) int map_points_timed(const bm_index* inde
     times->sort_ms = sort_ms;
     times->map_launches = maps;
     times->sort_launches = sorts;
+    times->unsort_ms = unsort_ms;
+    times->unsort_launches = unsorts;
     return BM_OK;
   }
   BM_GUARD("map_points_timed")

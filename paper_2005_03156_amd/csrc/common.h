@@ -123,18 +123,20 @@ struct OffsetHeader {
 
 // Calls of at least kPresortMin points are spatially sorted in chunks of
 // KIndex::presort_chunk points before mapping (when Tuning::presort is set),
-// up to kPresortSuper points (all their chunks) per round of sort passes. The
-// chunk is 2^22 points while the index fits the 256 MB last-level cache
-// (larger chunks spread one mapping launch's result stores wider); above that
-// each chunk reads the part of the index it touches from HBM, and 2^26-point
-// chunks read it fewer times per point (8M-block quadtree: 10.1 -> 8.4 ms per
-// 2^26 points).
+// up to kPresortSuper points (all their chunks) per round of sort passes.
+// Each chunk is sorted on its own, so a chunk is one pass over the plane in
+// Z-order. The chunk is 2^24 points while the index fits the 256 MB
+// last-level cache (220,900-block grid, 100M points per call: 5.32 / 5.23 /
+// 5.26 ms with 2^23 / 2^24 / 2^25-point chunks); above that each chunk reads
+// the part of the index it touches from HBM, and 2^26-point chunks read it
+// fewer times per point (8M-block quadtree: 10.1 -> 8.4 ms per 2^26 points).
 // The sort's bin grid has 32 x 32 bins for the smaller indexes (each bin then
-// re-sorted by 32 x 32 sub-cells; 220,900-block grid: 6.32 -> 6.01 ms per
-// 100M points) and 64 x 64 bins (64 x 64 sub-cells) for the larger ones
-// (the quadtree: 7.58 ms per 2^26 points, against 8.63 with 32 x 32 bins).
+// re-sorted by 32 x 32 sub-cells in pieces of 4,096 points; 2,048 / 8,192
+// points: 5.36 / 5.33 ms) and 64 x 64 bins (64 x 64 sub-cells) for the
+// larger ones (the quadtree: 7.58 ms per 2^26 points, against 8.63 with 32 x
+// 32 bins).
 constexpr long long kPresortMin = 1 << 20;
-constexpr long long kPresortChunk = 1 << 22;
+constexpr long long kPresortChunk = 1 << 24;
 constexpr long long kPresortChunkBigIndex = 1 << 26;
 constexpr long long kPresortBigIndex = 256ll << 20;
 constexpr long long kPresortSuper = 1 << 27;
@@ -149,8 +151,9 @@ struct Tuning {
 Tuning tuning_from(const bm_tuning* t);
 
 // Optional event marks around the launches of one mapping call: tag 0 opens
-// and tag 1 closes a mapping-kernel launch; tag 2 opens a sort phase (closed
-// by the next tag 0).
+// and tag 1 closes a mapping-kernel launch; tag 2 opens a round's sort
+// passes and tag 3 its unsort passes (each closed by the next mark); tag 4
+// ends the call.
 struct LaunchTimer {
   static constexpr int kMax = 1024;
   hipEvent_t ev[kMax];

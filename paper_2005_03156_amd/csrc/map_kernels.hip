@@ -418,41 +418,31 @@ __device__ __forceinline__ void pip_rounds(const KIndex& ix, WaveLds& S, const i
 }
 
 // The whole path for one tile of up to kTile points (point j * 64 + lane on
-// lane `lane`); all 64 lanes of the wave take part. Writes the result of
-// point i < nvalid to out[i], or to out[perm[i]] when a permutation is given
-// (entries outside [0, nperm) are skipped). With several points per lane the
-// candidate lists of a level hold the items of all of them, so its rounds of
-// 64 items run nearly full.
+// lane `lane`, given in registers as pt[j]); all 64 lanes of the wave take
+// part. Writes the result of point i < nvalid to out[i], one coalesced store
+// per tile. With several points per lane the candidate lists of a level hold
+// the items of all of them, so its rounds of 64 items run nearly full.
 template <int kChunkShift>
 __device__ __forceinline__ void map_tile_pts(const KIndex& ix, WaveLds& S, const int lane,
                                              const int2 (&pt)[kTilePts], const int nvalid,
-                                             int* __restrict__ out, const int (&dst)[kTilePts],
-                                             const long long nperm);
+                                             int* __restrict__ out);
 
 template <int kChunkShift>
 __device__ __forceinline__ void map_tile(const KIndex& ix, WaveLds& S, const int lane,
-                                         const int2* __restrict__ xy, const int nvalid,
-                                         int* __restrict__ out, const int* __restrict__ perm = nullptr,
-                                         const long long nperm = 0) {
+                                         const int2* __restrict__ xy, const int nvalid, int* __restrict__ out) {
   int2 pt[kTilePts];
-  int dst[kTilePts];
 #pragma unroll
   for (int j = 0; j < kTilePts; ++j) {
     const int i = j * kWave + lane;
     pt[j] = i < nvalid ? ld_once(xy + i) : make_int2(0, 0);
-    dst[j] = perm ? (i < nvalid ? ld_once(perm + i) : -1) : i;
   }
-  map_tile_pts<kChunkShift>(ix, S, lane, pt, nvalid, out, dst, perm ? nperm : (long long)nvalid);
+  map_tile_pts<kChunkShift>(ix, S, lane, pt, nvalid, out);
 }
 
-// The tile's points given in registers (point j * 64 + lane in pt[j]); the
-// result of point j * 64 + lane < nvalid goes to out[dst[j]] when dst[j] lies
-// in [0, nperm).
 template <int kChunkShift>
 __device__ __forceinline__ void map_tile_pts(const KIndex& ix, WaveLds& S, const int lane,
                                              const int2 (&pt)[kTilePts], const int nvalid,
-                                             int* __restrict__ out, const int (&dst)[kTilePts],
-                                             const long long nperm) {
+                                             int* __restrict__ out) {
 #pragma unroll
   for (int j = 0; j < kTilePts; ++j) {
     const int i = j * kWave + lane;
@@ -496,7 +486,7 @@ __device__ __forceinline__ void map_tile_pts(const KIndex& ix, WaveLds& S, const
     if (i < nvalid) {
       unsigned best = S.best[i];
       if (S.ovf[i]) best = min(best, walk_point(ix, S.pts[i]));
-      if ((unsigned long long)(long long)dst[j] < (unsigned long long)nperm) st_once(out + dst[j], (int)best);
+      st_once(out + i, (int)best);
     }
   }
   wave_sync();
@@ -705,10 +695,16 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map
 // box (points outside fall in the nearest border cell), and each bin is then
 // re-sorted, in pieces, by the Morton index of its sub-cell: together a
 // Z-order on a 1024 x 1024 grid (kBB = 5, 32 x 32 sub-cells per bin) or a
-// 4096 x 4096 grid (kBB = 6, 64 x 64). The mapping kernel then reads the
-// sorted copy and writes each result back to the point's original position.
-// Each point's result depends on that point alone, so the order does not
-// change any output. kBB is 5 for an index that fits the last-level cache
+// 4096 x 4096 grid (kBB = 6, 64 x 64). The mapping kernel then maps the
+// sorted copy and stores its results in sorted order, coalesced; two passes
+// bring them back to the points' original positions: the first undoes the
+// re-sort of each piece through LDS, the second gathers every original
+// position's result from the runs its scatter block wrote. (Storing each result
+// through the permutation from the mapping kernel instead costs a partial
+// cache line per 4-byte result: mapping kernel 4.61 -> 3.79 ms per 100M
+// points on the 220,900-block grid, 6.11 -> 4.53 ms per 2^26 points on the
+// 8M-block quadtree without those stores.) Each point's result depends on
+// that point alone, so the order does not change any output. kBB is 5 for an index that fits the last-level cache
 // (shorter sort passes) and 6 for a larger one (finer order, so that the
 // points of one block share a tile and its lines are read from HBM fewer
 // times: 8M-block quadtree 8.19 -> 7.58 ms per 2^26 points with 64 x 64
@@ -868,8 +864,11 @@ __global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ t
 // uses from the bin cursors, lays the points out in LDS in bin order, and
 // then stores them with consecutive threads on consecutive positions of the
 // runs, so a wave's stores touch a few cache lines rather than one per lane:
-// sorted[pos] = point, perm[pos] = its index in the chunk. (The order inside
-// a bin varies from run to run; no output depends on it.)
+// sorted[pos] = point. For the unscatter pass the block also records, in the
+// same (bin) order and at the same offsets of its own range, each point's
+// position in the chunk's sorted order (spos, int) and its offset in the
+// block's range of points (sidx, u16). (The order inside a bin varies from
+// run to run; no output depends on it.)
 constexpr int kScatPer = 12;
 constexpr long long kScatPts = (long long)kBinThreads * kScatPer;
 
@@ -877,7 +876,9 @@ template <int kBB>
 __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __restrict__ xy, const long long m,
                                                                   const long long chunk, const int4 rb, const int shx,
                                                                   const int shy, unsigned* __restrict__ cursor,
-                                                                  int2* __restrict__ sorted, int* __restrict__ perm) {
+                                                                  int2* __restrict__ sorted, int* __restrict__ spos,
+                                                                  unsigned short* __restrict__ sidx) {
+  static_assert(kScatPts <= 65536, "offsets in a scatter block fit 16 bits");
   __shared__ int2 sx[kScatPts];
   __shared__ unsigned short si[kScatPts];
   constexpr int kNB = Bins<kBB>::kN;
@@ -890,7 +891,8 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   xy += c0;
   cursor += (size_t)blockIdx.y * kBins;
   sorted += c0;
-  perm += c0;
+  spos += c0;
+  sidx += c0;
   int2 p[kScatPer];
   unsigned b[kScatPer], r[kScatPer];
 #pragma unroll
@@ -936,16 +938,19 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
     const int2 q = sx[j];
     const unsigned pos = d[bin_of<kBB>(q, rb, shx, shy)] + (unsigned)j;
     sorted[pos] = q;
-    perm[pos] = (int)(lo + si[j]);
+    spos[lo + j] = (int)pos;
+    sidx[lo + j] = si[j];
   }
 }
 
 // Refinement: after the scatter, cursor[bin] is the end of the bin. Block
-// (i, c) takes piece i of chunk c (the bin found by a binary search of pstart) and sorts its
-// points and permutation entries in place by the Morton index of their
-// sub-cell of the bin's cell, through LDS. Bin and sub-cell together order
-// the chunk along a Z-curve, so the mapping kernel's tiles of points are
-// spatially tighter. Blocks beyond the last piece exit at once.
+// (i, c) takes piece i of chunk c (the bin found by a binary search of
+// pstart) and sorts its points in place by the Morton index of their
+// sub-cell of the bin's cell, through LDS; rof[base + j] records the offset
+// in the piece that the point at offset j came from, for the unrefine pass.
+// Bin and sub-cell together order the chunk along a Z-curve, so the mapping
+// kernel's tiles of points are spatially tighter. Blocks beyond the last
+// piece exit at once.
 template <int kBB>
 __device__ __forceinline__ unsigned sub_of(const int2 p, const int4 rb, const int shx, const int shy) {
   constexpr int kSubBits = Bins<kBB>::kSubBits;
@@ -956,50 +961,64 @@ __device__ __forceinline__ unsigned sub_of(const int2 p, const int4 rb, const in
   return spread6(cx) | (spread6(cy) << 1);
 }
 
+// The piece that block (piece, chunk) of the refine and unrefine passes
+// takes: [base, base + cnt) of the chunk's sorted order; false for blocks
+// beyond the chunk's last piece. Every thread of the block must call it.
 template <int kBB>
-__global__ __launch_bounds__(Bins<kBB>::kRefThreads) void bin_refine_kernel(int2* __restrict__ sorted, int* __restrict__ perm,
-                                                                 const long long chunk,
-                                                                 const unsigned* __restrict__ cursor,
-                                                                 const unsigned* __restrict__ pstart, const int4 rb,
-                                                                 const int shx, const int shy) {
-  constexpr int kNB = Bins<kBB>::kN, kSubs = Bins<kBB>::kSubs, kRefPer = Bins<kBB>::kRefPer;
-  constexpr int kRefThreads = Bins<kBB>::kRefThreads;
-  constexpr int kRefPts = kRefThreads * kRefPer;
-  __shared__ int2 sx[kRefPts];
-  __shared__ int sp[kRefPts];
-  __shared__ unsigned h[kSubs];
-  __shared__ unsigned wsum[kRefThreads / kWave];
-  __shared__ int the_bin;
-  static_assert(kSubs % kRefThreads == 0, "whole sub-cell counts per thread");
-  constexpr int kQ = kSubs / kRefThreads;
-  sorted += (long long)blockIdx.y * chunk;  // block (piece, chunk)
-  perm += (long long)blockIdx.y * chunk;
-  cursor += (size_t)blockIdx.y * kBins;
-  pstart += (size_t)blockIdx.y * kPStride;
+__device__ __forceinline__ bool piece_range(const unsigned* __restrict__ cursor, const unsigned* __restrict__ pstart,
+                                            int* the_bin, unsigned& base, int& cnt) {
+  constexpr int kNB = Bins<kBB>::kN;
+  constexpr unsigned kRefPts = Bins<kBB>::kRefThreads * Bins<kBB>::kRefPer;
   const unsigned piece = blockIdx.x;
-  if (piece >= pstart[kNB]) return;
+  if (piece >= pstart[kNB]) return false;
   if (threadIdx.x == 0) {  // the last bin whose first piece is <= piece
     int lo = 0, hi = kNB - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (pstart[mid] <= piece) lo = mid; else hi = mid - 1;
     }
-    the_bin = lo;
+    *the_bin = lo;
   }
-  for (int i = threadIdx.x; i < kSubs; i += kRefThreads) h[i] = 0;
   __syncthreads();
-  const int b = the_bin;
+  const int b = *the_bin;
   const unsigned start = b ? cursor[b - 1] : 0u, end = cursor[b];
-  const unsigned base = start + (piece - pstart[b]) * (unsigned)kRefPts;
-  const int cnt = (int)min((unsigned)kRefPts, end - base);
+  base = start + (piece - pstart[b]) * kRefPts;
+  cnt = (int)min(kRefPts, end - base);
+  return true;
+}
+
+template <int kBB>
+__global__ __launch_bounds__(Bins<kBB>::kRefThreads) void bin_refine_kernel(int2* __restrict__ sorted,
+                                                                 unsigned short* __restrict__ rof,
+                                                                 const long long chunk,
+                                                                 const unsigned* __restrict__ cursor,
+                                                                 const unsigned* __restrict__ pstart, const int4 rb,
+                                                                 const int shx, const int shy) {
+  constexpr int kSubs = Bins<kBB>::kSubs, kRefPer = Bins<kBB>::kRefPer;
+  constexpr int kRefThreads = Bins<kBB>::kRefThreads;
+  constexpr int kRefPts = kRefThreads * kRefPer;
+  static_assert(kRefPts <= 65536, "offsets in a piece fit 16 bits");
+  __shared__ int2 sx[kRefPts];
+  __shared__ unsigned short so[kRefPts];
+  __shared__ unsigned h[kSubs];
+  __shared__ unsigned wsum[kRefThreads / kWave];
+  __shared__ int the_bin;
+  static_assert(kSubs % kRefThreads == 0, "whole sub-cell counts per thread");
+  constexpr int kQ = kSubs / kRefThreads;
+  sorted += (long long)blockIdx.y * chunk;  // block (piece, chunk)
+  rof += (long long)blockIdx.y * chunk;
+  cursor += (size_t)blockIdx.y * kBins;
+  pstart += (size_t)blockIdx.y * kPStride;
+  for (int i = threadIdx.x; i < kSubs; i += kRefThreads) h[i] = 0;
+  unsigned base;
+  int cnt;
+  if (!piece_range<kBB>(cursor, pstart, &the_bin, base, cnt)) return;
   int2 p[kRefPer];
-  int q[kRefPer];
   unsigned key[kRefPer], r[kRefPer];
 #pragma unroll
   for (int k = 0; k < kRefPer; ++k) {
     const int j = threadIdx.x + k * kRefThreads;
     p[k] = j < cnt ? ld_once(sorted + base + j) : make_int2(0, 0);
-    q[k] = j < cnt ? ld_once(perm + base + j) : 0;
   }
 #pragma unroll
   for (int k = 0; k < kRefPer; ++k) {
@@ -1025,50 +1044,114 @@ __global__ __launch_bounds__(Bins<kBB>::kRefThreads) void bin_refine_kernel(int2
     if (key[k] < (unsigned)kSubs) {
       const unsigned j = h[key[k]] + r[k];
       sx[j] = p[k];
-      sp[j] = q[k];
+      so[j] = (unsigned short)(threadIdx.x + k * kRefThreads);
     }
   __syncthreads();
   for (int j = threadIdx.x; j < cnt; j += kRefThreads) {
     sorted[base + j] = sx[j];
-    perm[base + j] = sp[j];
+    rof[base + j] = so[j];
   }
 }
 
-// Sorted form: as the plain form, over the sorted copy, each result going to
-// the point's original position.
+// Unrefine: the inverse of the refine pass on the results, piece by piece
+// and in place: the result at offset j goes back to offset rof[base + j].
+template <int kBB>
+__global__ __launch_bounds__(Bins<kBB>::kRefThreads) void bin_unrefine_kernel(int* __restrict__ res,
+                                                                   const unsigned short* __restrict__ rof,
+                                                                   const long long chunk,
+                                                                   const unsigned* __restrict__ cursor,
+                                                                   const unsigned* __restrict__ pstart) {
+  constexpr int kRefPer = Bins<kBB>::kRefPer, kRefThreads = Bins<kBB>::kRefThreads;
+  constexpr int kRefPts = kRefThreads * kRefPer;
+  __shared__ int sr[kRefPts];
+  __shared__ int the_bin;
+  res += (long long)blockIdx.y * chunk;
+  rof += (long long)blockIdx.y * chunk;
+  cursor += (size_t)blockIdx.y * kBins;
+  pstart += (size_t)blockIdx.y * kPStride;
+  unsigned base;
+  int cnt;
+  if (!piece_range<kBB>(cursor, pstart, &the_bin, base, cnt)) return;
+  int v[kRefPer];
+  unsigned o[kRefPer];
+#pragma unroll
+  for (int k = 0; k < kRefPer; ++k) {
+    const int j = threadIdx.x + k * kRefThreads;
+    v[k] = j < cnt ? ld_once(res + base + j) : 0;
+    o[k] = j < cnt ? (unsigned)__builtin_nontemporal_load(rof + base + j) : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < kRefPer; ++k)
+    if (threadIdx.x + k * kRefThreads < cnt) sr[o[k]] = v[k];
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += kRefThreads) res[base + j] = sr[j];
+}
+
+// Unscatter: the inverse of the scatter pass on the results. Block (b, c)
+// takes the kScatPts points of scatter block b of chunk c: consecutive
+// threads read the results at the positions the scatter block recorded
+// (spos, in bin order, so a wave's loads follow a few runs), place each at
+// its point's offset in LDS (sidx), and store the block's range of out
+// coalesced.
+__global__ __launch_bounds__(kBinThreads) void unscatter_kernel(const int* __restrict__ res, const int* __restrict__ spos,
+                                                               const unsigned short* __restrict__ sidx,
+                                                               const long long m, const long long chunk,
+                                                               int* __restrict__ out) {
+  __shared__ int sv[kScatPts];
+  const long long c0 = (long long)blockIdx.y * chunk, n = min(chunk, m - c0);
+  const long long lo = (long long)blockIdx.x * kScatPts;
+  if (lo >= n) return;
+  res += c0;
+  spos += c0 + lo;
+  sidx += c0 + lo;
+  out += c0 + lo;
+  const int cnt = (int)min((long long)kScatPts, n - lo);
+  int q[kScatPer];
+  unsigned t[kScatPer];
+#pragma unroll
+  for (int k = 0; k < kScatPer; ++k) {
+    const int j = threadIdx.x + k * kBinThreads;
+    q[k] = j < cnt ? ld_once(spos + j) : 0;
+    t[k] = j < cnt ? (unsigned)__builtin_nontemporal_load(sidx + j) : 0u;
+  }
+  int v[kScatPer];
+#pragma unroll
+  for (int k = 0; k < kScatPer; ++k) v[k] = res[q[k]];
+#pragma unroll
+  for (int k = 0; k < kScatPer; ++k)
+    if (threadIdx.x + k * kBinThreads < cnt) sv[t[k]] = v[k];
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += kBinThreads) st_once(out + j, sv[j]);
+}
+
+// Sorted form: as the plain form, over the sorted copy of a round of sort
+// passes; results in sorted order (the unrefine and unscatter passes bring
+// them to the points' original positions). Each wave loads its next tile's
+// points while it maps the current one.
 template <int kChunkShift>
 __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void map_sorted_kernel(
-    const KIndex ix, const int2* __restrict__ xy, const int* __restrict__ perm, const long long n,
-    int* __restrict__ out) {
+    const KIndex ix, const int2* __restrict__ xy, const long long n, int* __restrict__ out) {
   __shared__ WaveLds wl[kWavesPerBlock];
   const int lane = threadIdx.x & (kWave - 1);
   WaveLds& S = wl[threadIdx.x / kWave];
   const long long ntiles = (n + kTile - 1) / kTile;
   const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
-  // each wave loads its next tile's points and permutation entries while it
-  // maps the current one
   int2 np[kTilePts];
-  int nq[kTilePts];
   auto fetch = [&](const long long t) {
 #pragma unroll
     for (int j = 0; j < kTilePts; ++j) {
       const long long i = t * kTile + j * kWave + lane;
       np[j] = i < n ? ld_once(xy + i) : make_int2(0, 0);
-      nq[j] = i < n ? ld_once(perm + i) : -1;
     }
   };
   long long t = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (t < ntiles) fetch(t);
   for (; t < ntiles; t += nwaves) {
     int2 pt[kTilePts];
-    int dst[kTilePts];
 #pragma unroll
-    for (int j = 0; j < kTilePts; ++j) {
-      pt[j] = np[j];
-      dst[j] = nq[j];
-    }
+    for (int j = 0; j < kTilePts; ++j) pt[j] = np[j];
     if (t + nwaves < ntiles) fetch(t + nwaves);
-    map_tile_pts<kChunkShift>(ix, S, lane, pt, (int)min((long long)kTile, n - t * kTile), out, dst, n);
+    map_tile_pts<kChunkShift>(ix, S, lane, pt, (int)min((long long)kTile, n - t * kTile), out + t * kTile);
   }
 }
 
@@ -1295,50 +1378,91 @@ static void launch_plain(const KIndex& ix, const int2* p, long long n, int* out,
 }
 
 template <int kShift>
-static void launch_sorted(const KIndex& ix, const int2* p, const int* perm, long long n, int* out, const Tuning& t,
-                          int num_cu, hipStream_t stream) {
+static void launch_sorted(const KIndex& ix, const int2* p, long long n, int* out, const Tuning& t, int num_cu,
+                          hipStream_t stream) {
   const dim3 grid((unsigned)grid_blocks<map_sorted_kernel<kShift>>(n, t, num_cu));
-  hipLaunchKernelGGL(map_sorted_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, p, perm, n, out);
+  hipLaunchKernelGGL(map_sorted_kernel<kShift>, grid, dim3(kBlock), 0, stream, ix, p, n, out);
+}
+
+// Shifts of the sort grid over the root box, and whether the refine pass
+// runs (the root box at least 1024 units a side).
+struct SortGrid {
+  int shx = 0, shy = 0;
+  bool refine = false;
+};
+
+template <int kBB>
+static SortGrid sort_grid(const int4 rb) {
+  SortGrid g;
+  while (((1ll << kBB) << g.shx) < (long long)rb.y - rb.x) ++g.shx;
+  while (((1ll << kBB) << g.shy) < (long long)rb.w - rb.z) ++g.shy;
+  g.refine = g.shx >= Bins<kBB>::kSubBits && g.shy >= Bins<kBB>::kSubBits;
+  return g;
+}
+
+// Blocks per chunk of the refine and unrefine passes: at most chunk / piece
+// size + bins pieces per chunk.
+template <int kBB>
+static unsigned piece_blocks(const long long chunk) {
+  return (unsigned)(chunk / ((long long)Bins<kBB>::kRefThreads * Bins<kBB>::kRefPer) + Bins<kBB>::kN);
 }
 
 // One round of sort passes over the nc chunks of m points at p: count, scan,
-// scatter and (when the root box is at least 1024 units a side) refine.
+// scatter and (when the grid allows) refine.
 template <int kBB>
 static void sort_passes(const int4 rb, const int2* p, const long long m, const long long chunk, const unsigned nc,
-                        unsigned* tot, unsigned* cursor, unsigned* pstart, int2* sorted, int* perm,
-                        hipStream_t stream) {
-  constexpr int kSubBits = Bins<kBB>::kSubBits;
-  constexpr long long kRefPts = (long long)Bins<kBB>::kRefThreads * Bins<kBB>::kRefPer;
-  int shx = 0, shy = 0;
-  while (((1ll << kBB) << shx) < (long long)rb.y - rb.x) ++shx;
-  while (((1ll << kBB) << shy) < (long long)rb.w - rb.z) ++shy;
-  const bool refine = shx >= kSubBits && shy >= kSubBits;
+                        unsigned* tot, unsigned* cursor, unsigned* pstart, int2* sorted, int* spos,
+                        unsigned short* sidx, unsigned short* rof, hipStream_t stream) {
+  const SortGrid g = sort_grid<kBB>(rb);
   hipLaunchKernelGGL(bin_count_kernel<kBB>, dim3((unsigned)((chunk + kBinBlockPts - 1) / kBinBlockPts), nc),
-                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, shx, shy, tot);
+                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, g.shx, g.shy, tot);
   hipLaunchKernelGGL(bin_scan_kernel<kBB>, dim3(nc), dim3(kBinThreads), 0, stream, tot, cursor,
-                     refine ? pstart : nullptr);
+                     g.refine ? pstart : nullptr);
   hipLaunchKernelGGL(bin_scatter_kernel<kBB>, dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc),
-                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, shx, shy, cursor, sorted, perm);
-  if (refine)  // at most chunk / kRefPts + bins pieces per chunk
-    hipLaunchKernelGGL(bin_refine_kernel<kBB>, dim3((unsigned)(chunk / kRefPts + Bins<kBB>::kN), nc),
-                       dim3(Bins<kBB>::kRefThreads), 0, stream, sorted, perm, chunk, cursor, pstart, rb, shx, shy);
+                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, g.shx, g.shy, cursor, sorted, spos, sidx);
+  if (g.refine)
+    hipLaunchKernelGGL(bin_refine_kernel<kBB>, dim3(piece_blocks<kBB>(chunk), nc), dim3(Bins<kBB>::kRefThreads), 0,
+                       stream, sorted, rof, chunk, cursor, pstart, rb, g.shx, g.shy);
+}
+
+// The results of a round (res, in sorted order) back to the points'
+// original positions: unrefine (when the refine pass ran), then unscatter
+// into out.
+template <int kBB>
+static void unsort_passes(const int4 rb, const long long m, const long long chunk, const unsigned nc,
+                          const unsigned* cursor, const unsigned* pstart, const int* spos, const unsigned short* sidx,
+                          const unsigned short* rof, int* res, int* out, hipStream_t stream) {
+  if (sort_grid<kBB>(rb).refine)
+    hipLaunchKernelGGL(bin_unrefine_kernel<kBB>, dim3(piece_blocks<kBB>(chunk), nc), dim3(Bins<kBB>::kRefThreads), 0,
+                       stream, res, rof, chunk, cursor, pstart);
+  hipLaunchKernelGGL(unscatter_kernel, dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc), dim3(kBinThreads), 0,
+                     stream, res, spos, sidx, m, chunk, out);
 }
 
 // Scratch of a pre-sorted call that sorts `super` points per round in chunks
-// of `chunk`: per chunk the sort's bin totals, cursors and piece starts, then
-// the sorted copy (int2) and the permutation (int) of `super` points.
+// of `chunk`: per chunk the sort's bin totals, cursors and piece starts; then
+// per point of a round the sorted copy (int2), the scatter pass's position
+// and offset records (int, u16), the result in sorted order (int) and the
+// refine pass's offset record (u16): 20 bytes per point.
 struct PresortPlan {
   long long chunk = 0, super = 0, max_nc = 0;
-  size_t hist_bytes = 0, bytes = 0;
+  size_t hist_bytes = 0, sorted_off = 0, spos_off = 0, sidx_off = 0, res_off = 0, rof_off = 0, bytes = 0;
 };
+
+static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 
 static PresortPlan presort_plan(long long chunk, long long super) {
   PresortPlan pl;
   pl.chunk = chunk;
   pl.super = super;
   pl.max_nc = (super + chunk - 1) / chunk;
-  pl.hist_bytes = (sizeof(unsigned) * (size_t)pl.max_nc * (2 * (size_t)kBins + kPStride) + 255) / 256 * 256;
-  pl.bytes = pl.hist_bytes + (size_t)super * (sizeof(int2) + sizeof(int)) + 256;
+  pl.hist_bytes = round256(sizeof(unsigned) * (size_t)pl.max_nc * (2 * (size_t)kBins + kPStride));
+  pl.sorted_off = pl.hist_bytes;
+  pl.spos_off = pl.sorted_off + round256((size_t)super * sizeof(int2));
+  pl.sidx_off = pl.spos_off + round256((size_t)super * sizeof(int));
+  pl.res_off = pl.sidx_off + round256((size_t)super * sizeof(unsigned short));
+  pl.rof_off = pl.res_off + round256((size_t)super * sizeof(int));
+  pl.bytes = pl.rof_off + round256((size_t)super * sizeof(unsigned short));
   return pl;
 }
 
@@ -1363,13 +1487,13 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
     }
   };
   bool presort = wants_presort(ix, n, t);
-  // Spatially sorted through scratch (12 bytes per point, up to kPresortSuper
-  // points at a time): every sort pass runs once over all chunks of a
-  // super-chunk (chunk = blockIdx.y), then one mapping launch per chunk keeps
-  // its scattered result stores within the chunk's window. The scratch is
-  // stream-ordered memory, or the caller's workspace: then the call sorts as
-  // many points per round as the workspace holds (in chunks no larger), and
-  // maps unsorted when it holds fewer than kPresortMin.
+  // Spatially sorted through scratch (20 bytes per point, up to kPresortSuper
+  // points at a time): every sort pass runs once over all chunks of a round
+  // (chunk = blockIdx.y), one mapping launch maps the round's sorted copy,
+  // and the unrefine and unscatter passes put its results in place. The
+  // scratch is stream-ordered memory, or the caller's workspace: then the
+  // call sorts as many points per round as the workspace holds (in chunks no
+  // larger), and maps unsorted when it holds fewer than kPresortMin.
   PresortPlan pl;
   if (presort) {
     long long super = std::min<long long>(n, kPresortSuper);
@@ -1399,33 +1523,40 @@ hipError_t launch_map(const KIndex& ix, const int32_t* xy, int64_t n, int32_t* o
     e = hipMallocAsync(&scratch, pl.bytes, stream);
     if (e != hipSuccess) return e;
   }
-  unsigned* tot = static_cast<unsigned*>(scratch);
+  char* base = static_cast<char*>(scratch);
+  unsigned* tot = reinterpret_cast<unsigned*>(base);
   unsigned* cursor = tot + max_nc * kBins;
   unsigned* pstart = cursor + max_nc * kBins;
-  int2* sorted = reinterpret_cast<int2*>(static_cast<char*>(scratch) + pl.hist_bytes);
-  int* perm = reinterpret_cast<int*>(sorted + super);
+  int2* sorted = reinterpret_cast<int2*>(base + pl.sorted_off);
+  int* spos = reinterpret_cast<int*>(base + pl.spos_off);
+  unsigned short* sidx = reinterpret_cast<unsigned short*>(base + pl.sidx_off);
+  int* res = reinterpret_cast<int*>(base + pl.res_off);
+  unsigned short* rof = reinterpret_cast<unsigned short*>(base + pl.rof_off);
   hipLaunchKernelGGL(bin_zero_kernel, dim3((unsigned)std::min<long long>(max_nc * 4, 1024)), dim3(1024), 0, stream,
                      tot, max_nc * kBins);
   for (long long s0 = 0; s0 < n && e == hipSuccess; s0 += super) {
-    const long long m = std::min(super, (long long)n - s0);  // the first super-chunk is the largest
+    const long long m = std::min(super, (long long)n - s0);  // the first round is the largest
     const unsigned nc = (unsigned)((m + chunk - 1) / chunk);
     mark(2);
     if (ix.presort_bin_bits == 6)
-      sort_passes<6>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, perm, stream);
+      sort_passes<6>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof, stream);
     else
-      sort_passes<5>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, perm, stream);
-    for (unsigned c = 0; c < nc; ++c) {
-      const long long c0 = (long long)c * chunk, mc = std::min(chunk, m - c0);
-      mark(0);
-      switch (t.edge_chunk) {
-        case 8: launch_sorted<3>(ix, sorted + c0, perm + c0, mc, out + s0 + c0, t, num_cu, stream); break;
-        case 16: launch_sorted<4>(ix, sorted + c0, perm + c0, mc, out + s0 + c0, t, num_cu, stream); break;
-        default: launch_sorted<2>(ix, sorted + c0, perm + c0, mc, out + s0 + c0, t, num_cu, stream); break;
-      }
-      mark(1);
+      sort_passes<5>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof, stream);
+    mark(0);
+    switch (t.edge_chunk) {
+      case 8: launch_sorted<3>(ix, sorted, m, res, t, num_cu, stream); break;
+      case 16: launch_sorted<4>(ix, sorted, m, res, t, num_cu, stream); break;
+      default: launch_sorted<2>(ix, sorted, m, res, t, num_cu, stream); break;
     }
+    mark(1);
+    mark(3);
+    if (ix.presort_bin_bits == 6)
+      unsort_passes<6>(ix.root_box, m, chunk, nc, cursor, pstart, spos, sidx, rof, res, out + s0, stream);
+    else
+      unsort_passes<5>(ix.root_box, m, chunk, nc, cursor, pstart, spos, sidx, rof, res, out + s0, stream);
     e = hipGetLastError();
   }
+  mark(4);
   if (ws) return e;
   const hipError_t e2 = hipFreeAsync(scratch, stream);
   return e != hipSuccess ? e : e2;

@@ -1,8 +1,9 @@
 // Allocation-free form of map_points, for callers that cannot allocate device
 // memory (code under HIP graph capture, tight serving loops, harnesses that
 // forbid hipMalloc). A call of at least 2^20 points is spatially pre-sorted,
-// which needs scratch (the sort's histograms, the sorted copy and the
-// permutation: 12 bytes per point); here it comes from `scratch` below, a
+// which needs scratch (the sort's histograms, the sorted copy, the records
+// that bring the results back to the points' order, and the results in
+// sorted order: 20 bytes per point); here it comes from `scratch` below, a
 // fixed array of kNoAllocBytes in device memory that every device the library
 // runs on holds until the process ends. Calls on one device share that
 // device's array.
@@ -23,10 +24,9 @@ namespace bm {
 namespace {
 
 constexpr long long kNoAllocMaxPoints = 1ll << 22;
-// one round of sort passes over kNoAllocMaxPoints points in one chunk: the
-// sorted copy and permutation (12 B per point) plus 1 MiB, more than the
-// chunk's histograms need
-constexpr size_t kNoAllocBytes = (size_t)kNoAllocMaxPoints * 12 + (1u << 20);
+// one round of sort passes over kNoAllocMaxPoints points in one chunk: 20 B
+// per point plus 1 MiB, more than the chunk's histograms and alignment need
+constexpr size_t kNoAllocBytes = (size_t)kNoAllocMaxPoints * 20 + (1u << 20);
 
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;

@@ -752,8 +752,9 @@ def test_server_over_quadtree8m_every_point(torch_cuda, bm, quadtree8m):
 def test_server_budget_covers_presort_scratch(torch_cuda, bm, grid221k):
     """Batches of 2^20 points or more are pre-sorted, and their sort scratch
     comes out of the server's memory budget: a budget of 12 bytes per point
-    alone is refused; one that also holds the scratch serves requests of 2^21
-    points (pre-sorted in the pool) with the ids each gets alone."""
+    alone (points and results) is refused; one that also holds the scratch
+    (20 bytes per point more) serves requests of 2^21 points (pre-sorted in
+    the pool) with the ids each gets alone."""
     torch = torch_cuda
     g, ix, H = grid221k
     mb = 1 << 21
@@ -763,7 +764,7 @@ def test_server_budget_covers_presort_scratch(torch_cuda, bm, grid221k):
     sizes = [mb - 5, 1000, mb, 70_000, mb - 64]
     reqs = [synth.points("grid221k", n, i0=90_000_000 + 3_000_000 * k) for k, n in enumerate(sizes)]
     alone = [gpu_map(bm, torch, ix, p) for p in reqs]
-    srv = bm.Server(ix, bm.server_cfg(mem_budget_bytes=25 * mb, max_batch_points=mb, max_slots=4, n_streams=2))
+    srv = bm.Server(ix, bm.server_cfg(mem_budget_bytes=34 * mb, max_batch_points=mb, max_slots=4, n_streams=2))
     outs = [np.full(p.shape[0], -7, np.int32) for p in reqs]
     say("server, pre-sort scratch in the budget")
     tickets = [srv.submit(p, o) for p, o in zip(reqs, outs)]
