@@ -563,7 +563,7 @@ def bench_served(bm, torch, g, ix, nreq, runs="all"):
 
     base_cfg = bm.server_cfg(mem_budget_bytes=2 << 30, max_batch_points=1 << 24, max_slots=1, n_streams=1,
                              flags=bm.BM_SERVER_ONE_PER_BATCH)
-    srv_cfg = bm.server_cfg(mem_budget_bytes=2 << 30, max_batch_points=1 << 23, max_slots=6, n_streams=4)
+    srv_cfg = bm.server_cfg(mem_budget_bytes=2 << 30, max_batch_points=1 << 22, max_slots=8, n_streams=8)
     zero = np.zeros(nreq)
     res = {"requests": nreq, "mean_points_per_request": mean_pts, "output_buffers": "one per submission"}
     if bpp is not None:

@@ -304,6 +304,10 @@ typedef struct {
   int32_t queue_capacity;    /* queued request pieces before submit returns BM_EBUSY */
   int32_t flags;             /* BM_SERVER_* */
   bm_tuning tuning;          /* launch shape of the mapping kernel */
+  int32_t copy_threads;      /* host threads (1..64, the server's own two included) that pack
+                                request pieces into the pinned pool and results out of it */
+  int64_t direct_min_points; /* pieces of at least this many points whose caller buffers are
+                                page-locked are copied by DMA directly, not packed (>= 1) */
 } bm_server_cfg;
 
 int bm_server_cfg_default(bm_server_cfg* cfg);

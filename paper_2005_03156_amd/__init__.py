@@ -85,7 +85,8 @@ class Batch(C.Structure):
 class ServerCfg(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("max_batch_points", C.c_int64), ("max_slots", C.c_int32),
                 ("n_streams", C.c_int32), ("coalesce_us", C.c_int32), ("queue_capacity", C.c_int32),
-                ("flags", C.c_int32), ("tuning", Tuning)]
+                ("flags", C.c_int32), ("tuning", Tuning), ("copy_threads", C.c_int32),
+                ("direct_min_points", C.c_int64)]
 
 
 class ServerStats(C.Structure):

@@ -3,13 +3,16 @@
 // Requests (host buffers of points) queue in FIFO order. A dispatcher thread
 // forms device batches from the head of the queue as soon as a batch slot and
 // enough pool memory are free: the batch's points are packed contiguously into
-// a pinned host pool, copied to the same offsets of a device pool, mapped with
-// one plain kernel launch over the concatenation, and copied back, all on one
-// of several streams, so batches overlap on the device. A batch's pool range
+// a pinned host pool (by a few copy threads at once), copied to the same
+// offsets of a device pool, mapped with one plain kernel launch over the
+// concatenation, and copied back, all on one of several streams, so batches
+// overlap on the device. Large pieces in page-locked caller memory skip the
+// packing: they are copied by DMA straight to and from their place in the
+// device pool. A batch's pool range
 // also holds the mapping call's pre-sort scratch, so the memory budget bounds
 // everything the server uses on the device. A completion thread retires
 // whichever in-flight batch has finished, scatters results to the callers'
-// buffers, releases pool memory and slots, and records each request's latency.
+// buffers (with the copy threads), releases pool memory and slots, and records each request's latency.
 // Requests larger than a batch are split into pieces; a request completes when
 // its last piece does. Results are those of map_points on each request alone.
 // After a device error the server fails every queued piece and dispatches no
@@ -32,6 +35,7 @@
 #include <vector>
 
 #include "common.h"
+#include "copy_pool.h"
 #include "trace.h"
 
 using namespace bm;
@@ -106,11 +110,6 @@ struct Batch {
   int status = BM_OK;
 };
 
-// Pieces at least this large whose caller buffers are page-locked are copied
-// by DMA straight between the caller's memory and the device pool; smaller
-// ones are packed through the pinned pool by the CPU.
-constexpr int64_t kDirectMin = 1 << 14;
-
 bool is_pinned(const void* p) {
   if (!p) return false;
   hipPointerAttribute_t a;
@@ -130,6 +129,7 @@ struct bm_server {
   char* h_pool = nullptr;
   int64_t pool_bytes = 0;
   PoolAlloc* alloc = nullptr;
+  CopyPool* copies = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;  // one per slot
   std::vector<int> free_slots;
@@ -238,15 +238,21 @@ void bm_server::dispatch_loop() {
         e = hipMemcpyAsync(dx + 8 * run0, hx + 8 * run0, 8 * (size_t)(end - run0), hipMemcpyHostToDevice, s);
       run0 = -1;
     };
-    for (size_t k = 0; k < b->pieces.size(); ++k) {
-      const Piece& p = b->pieces[k];
-      if (p.r->pinned_in && p.n >= kDirectMin) {
+    auto direct_in = [&](const Piece& p) { return p.r->pinned_in && p.n >= cfg.direct_min_points; };
+    std::vector<CopyPool::Copy> pack;
+    for (const Piece& p : b->pieces) {
+      if (!direct_in(p)) pack.push_back(CopyPool::Copy{p.r->xy + 2 * p.first, hx + 8 * pos, 8 * (size_t)p.n});
+      pos += p.n;
+    }
+    copies->run(pack);
+    pos = 0;
+    for (const Piece& p : b->pieces) {
+      if (direct_in(p)) {
         flush_run(pos);
         if (e == hipSuccess)
           e = hipMemcpyAsync(dx + 8 * pos, p.r->xy + 2 * p.first, 8 * (size_t)p.n, hipMemcpyHostToDevice, s);
-      } else {
-        memcpy(hx + 8 * pos, p.r->xy + 2 * p.first, 8 * (size_t)p.n);
-        if (run0 < 0) run0 = pos;
+      } else if (run0 < 0) {
+        run0 = pos;
       }
       pos += p.n;
     }
@@ -265,7 +271,7 @@ void bm_server::dispatch_loop() {
     };
     for (size_t k = 0; k < b->pieces.size(); ++k) {
       const Piece& p = b->pieces[k];
-      if (p.r->pinned_out && p.n >= kDirectMin) {
+      if (p.r->pinned_out && p.n >= cfg.direct_min_points) {
         flush_out(pos);
         b->direct_out[k] = 1;
         if (e == hipSuccess)
@@ -324,12 +330,14 @@ void bm_server::complete_loop() {
     const int st = b->status;
     if (st == BM_OK) {
       const char* ho = h_pool + b->off + align_up(8 * b->npts);
+      std::vector<CopyPool::Copy> unpack;
       int64_t pos = 0;
       for (size_t k = 0; k < b->pieces.size(); ++k) {
         const Piece& p = b->pieces[k];
-        if (!b->direct_out[k]) memcpy(p.r->out + p.first, ho + 4 * pos, 4 * (size_t)p.n);
+        if (!b->direct_out[k]) unpack.push_back(CopyPool::Copy{ho + 4 * pos, p.r->out + p.first, 4 * (size_t)p.n});
         pos += p.n;
       }
+      copies->run(unpack);
     }
     const auto now = Clock::now();
     bm::trace_pop();
@@ -367,6 +375,8 @@ __attribute__((visibility("default"))) int bm_server_cfg_default(bm_server_cfg* 
   c->queue_capacity = 1 << 20;
   c->flags = 0;
   bm_tuning_default(&c->tuning);
+  c->copy_threads = 8;
+  c->direct_min_points = (int64_t)1 << 16;
   return BM_OK;
 }
 
@@ -380,7 +390,8 @@ __attribute__((visibility("default"))) int bm_server_create(const bm_index* inde
     bm_server_cfg_default(&c);
     if (cfg) c = *cfg;
     if (c.max_batch_points < 64 || c.max_slots < 1 || c.max_slots > 64 || c.n_streams < 1 || c.n_streams > 16 ||
-        c.queue_capacity < 1 || c.coalesce_us < 0)
+        c.queue_capacity < 1 || c.coalesce_us < 0 || c.copy_threads < 1 || c.copy_threads > 64 ||
+        c.direct_min_points < 1)
       return fail(BM_EINVAL, "bm_server_create: configuration out of range");
     const int64_t full_batch = align_up(8 * c.max_batch_points) + align_up(4 * c.max_batch_points) +
                                align_up((int64_t)map_scratch_bytes(index->k, c.max_batch_points, tuning_from(&c.tuning)));
@@ -425,6 +436,7 @@ __attribute__((visibility("default"))) int bm_server_create(const bm_index* inde
                   std::string("bm_server_create: ") + hipGetErrorString(e));
     }
     s->alloc = new PoolAlloc(s->pool_bytes);
+    s->copies = new CopyPool(c.copy_threads);
     s->dispatcher = std::thread([s] { s->dispatch_loop(); });
     s->completer = std::thread([s] { s->complete_loop(); });
     *out = s;
@@ -440,7 +452,8 @@ __attribute__((visibility("default"))) int bm_server_submit(bm_server* s, const 
     if (!s || !ticket) return fail(BM_EINVAL, "bm_server_submit: null argument");
     if (n < 0) return fail(BM_EINVAL, "bm_server_submit: n < 0");
     if (n > 0 && (!xy || !out)) return fail(BM_EINVAL, "bm_server_submit: null buffer");
-    const bool pin_in = n >= kDirectMin && is_pinned(xy), pin_out = n >= kDirectMin && is_pinned(out);
+    const bool pin_in = n >= s->cfg.direct_min_points && is_pinned(xy);
+    const bool pin_out = n >= s->cfg.direct_min_points && is_pinned(out);
     std::lock_guard<std::mutex> g(s->mu);
     if (s->fatal != BM_OK) return fail(s->fatal, s->fatal_msg);
     const int64_t np = n == 0 ? 0 : (n + s->cfg.max_batch_points - 1) / s->cfg.max_batch_points;
@@ -577,6 +590,7 @@ __attribute__((visibility("default"))) void bm_server_destroy(bm_server* s) {
   (void)hipFree(s->d_pool);
   (void)hipHostFree(s->h_pool);
   delete s->alloc;
+  delete s->copies;
   delete s;
 }
 

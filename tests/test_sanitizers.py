@@ -1,9 +1,10 @@
-"""The CPU oracle and the host-side index and cell-cover builders, built with
-AddressSanitizer and UndefinedBehaviorSanitizer (host code only: nothing
-here touches a GPU). Any sanitizer report aborts the program, so each run
-must exit cleanly, and each must give exactly what the ordinary builds give:
-the oracle's three routes per point, and the index and cover files byte for
-byte."""
+"""Host code under sanitizers (nothing here touches a GPU): the CPU oracle
+and the host-side index and cell-cover builders built with AddressSanitizer
+and UndefinedBehaviorSanitizer, each giving exactly what the ordinary builds
+give (the oracle's three routes per point; the index and cover files byte
+for byte); and the served form's host copy pool under ThreadSanitizer and
+AddressSanitizer. Any sanitizer report aborts the program, so each run must
+exit cleanly."""
 import os
 import subprocess
 
@@ -124,3 +125,21 @@ def test_index_and_cover_builders_under_sanitizers(drivers, case, keep):
     if not keep:  # the cover builds its own index with the default levels
         bm.build_cover_file(want_cv, vo, vv, ng, par, 0, 4)
         assert open(got_cv, "rb").read() == open(want_cv, "rb").read(), name
+
+
+@pytest.mark.parametrize("san", ["thread", "address"])
+def test_copy_pool_under_sanitizers(tmp_path, san):
+    """The served form's host copy pool (several callers at once, long copies
+    cut and shared out over the workers) under ThreadSanitizer and
+    AddressSanitizer: every destination byte right, no report."""
+    exe = str(tmp_path / ("copy_pool_" + san))
+    flags = ["-fsanitize=" + san, "-fno-omit-frame-pointer", "-g", "-O1"]
+    r = subprocess.run(["g++", "-std=c++17", *flags, "-I" + CSRC, os.path.join(HERE, "sanitize", "copy_pool_driver.cpp"),
+                        "-o", exe, "-lpthread"], capture_output=True, text=True)
+    if r.returncode:
+        pytest.skip("no %s sanitizer runtime for g++ here" % san)
+    for threads, callers, rounds in ((6, 4, 40), (1, 3, 10), (3, 8, 20)):
+        r = subprocess.run([exe, str(threads), str(callers), str(rounds)], env=ENV, capture_output=True, text=True,
+                           timeout=600)
+        assert r.returncode == 0, (san, threads, callers, r.stdout[-500:], r.stderr[-3000:])
+        assert " 0 wrong copies" in r.stdout
