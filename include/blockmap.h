@@ -203,9 +203,15 @@ int map_points_tuned(const bm_index* index, const int32_t* xy, int64_t n, int32_
                      const bm_tuning* t, hipStream_t stream);
 
 /* Pick a launch shape by timing candidates on a sample of points (device
- * pointer, n >= 64) with this index; the choice is cached per (device
- * architecture, index shape, size class) in the file named by the environment
- * variable BM_TUNE_CACHE (default $HOME/.cache/blockmap_tune.txt; unreadable or
+ * pointer, n >= 64) with this index: edge_chunk and blocks_per_cu (6 shapes)
+ * and presort (on or off, for samples of 2^20 points or more) by timing
+ * map_points_tuned on the sample; then tile_points (3 sizes) by timing the
+ * batched form on the sample cut into 16 batches. The batched form uses
+ * edge_chunk, blocks_per_cu and tile_points; it never pre-sorts (its batches
+ * are mapped in their own order), so presort only matters to
+ * map_points_tuned. The choice is cached per (device architecture, index
+ * shape, size class) in the file named by the environment variable
+ * BM_TUNE_CACHE (default $HOME/.cache/blockmap_tune.txt; unreadable or
  * unwritable cache files are ignored). Runs and synchronises on `stream`.
  * Errors: BM_EINVAL, BM_EHIP. */
 int bm_autotune(const bm_index* index, const int32_t* sample_xy, int64_t n, bm_tuning* out,
