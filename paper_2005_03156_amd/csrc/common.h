@@ -31,17 +31,38 @@ struct alignas(32) GroupRec {
 // A block's ring is reached through y-slabs: its y-extent [ymin, ymax) is cut
 // into K = 2^logK slabs of height 2^sh, and slab s lists, as ready vertex
 // pairs (a.x, a.y, b.x, b.y), the ring edges whose y-span overlaps it.
-struct alignas(64) LeafRec {
+//
+// The record also holds a map of the block's box cut into 16 x 16 cells of
+// 2^sx x 2^sy units (the smallest power-of-two sides with 16 cells covering
+// each side; kLeafCells, cell_shift): 2 bits per cell, row r in cell[r], column
+// c in bits 2c..2c+1. A cell whose closed rectangle meets no ring edge
+// (horizontal edges included) gives every point in it the same answer, found
+// once at index build: kCellOut (no point of the cell is in the block) or
+// kCellIn (every point is); other cells are kCellTest (run the crossing test).
+// A (block, point) pair whose point lies in an In or Out cell needs none of
+// the block's edges.
+constexpr int kLeafCells = 16;
+constexpr unsigned kCellOut = 0, kCellIn = 1, kCellTest = 2;
+struct alignas(128) LeafRec {
   int4 box;
   long long ent;       // index in `ent` of the leaf's first listed edge
   int leaf_id;         // block index as given by the caller
   int packed;          // sh | logK << 8 | kLeafExtOff when the offsets are not inline
   unsigned char off[32];  // inline slab offsets (K + 1 <= 32, all <= 255), relative to ent
+  uint32_t cell[kLeafCells];  // cell classes, 2 bits per cell
 };
 constexpr int kLeafExtOff = 1 << 24;  // offsets are K + 1 uint32 stored in the int4s before ent
-static_assert(sizeof(GroupRec) == 32 && sizeof(LeafRec) == 64, "record sizes");
+static_assert(sizeof(GroupRec) == 32 && sizeof(LeafRec) == 128, "record sizes");
 static_assert(offsetof(LeafRec, ent) == 16 && offsetof(LeafRec, leaf_id) == 24 && offsetof(LeafRec, packed) == 28,
               "the kernels read ent, leaf_id and packed as one int4");
+static_assert(offsetof(LeafRec, cell) == 64, "cell map in the record's second half");
+
+// Shift of the cell side along an axis of extent w >= 1 units: the smallest
+// s >= 0 with kLeafCells << s >= w (the same on host and device).
+__host__ __device__ inline int cell_shift(const unsigned w) {
+  const int bits = w > 1u ? 32 - __builtin_clz(w - 1u) : 0;  // ceil(log2 w)
+  return bits > 4 ? bits - 4 : 0;
+}
 
 // A wavefront maps a tile of 64 * kTilePts points (kTilePts per lane).
 // Kernel-side limits: a candidate item packs a node id with the point's slot

@@ -64,36 +64,6 @@ inline int64_t floor_div(int64_t a, int64_t b) {  // b > 0
 
 inline int tag_of(uint32_t v) { return v == kCoverEmpty ? 3 : (int)(v >> 30); }
 
-// Does segment a-b meet the closed square [qx0, qx1] x [qy0, qy1]? Exact:
-// the boxes must overlap and the four corners must not lie strictly on one
-// side of the line.
-bool seg_meets_square(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t qx0, int64_t qy0, int64_t qx1,
-                      int64_t qy1) {
-  if (std::max(ax, bx) < qx0 || std::min(ax, bx) > qx1 || std::max(ay, by) < qy0 || std::min(ay, by) > qy1)
-    return false;
-  const __int128 dx = bx - ax, dy = by - ay;
-  auto side = [&](int64_t px, int64_t py) {
-    const __int128 c = dx * (__int128)(py - ay) - dy * (__int128)(px - ax);
-    return (c > 0) - (c < 0);
-  };
-  const int s0 = side(qx0, qy0), s1 = side(qx1, qy0), s2 = side(qx0, qy1), s3 = side(qx1, qy1);
-  if (s0 > 0 && s1 > 0 && s2 > 0 && s3 > 0) return false;
-  if (s0 < 0 && s1 < 0 && s2 < 0 && s3 < 0) return false;
-  return true;
-}
-
-// The crossing rule for one edge and a point inside the edge's block box
-// (the predicate the kernels evaluate).
-inline unsigned crosses_host(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t px, int64_t py) {
-  const bool a_up = ay > py, b_up = by > py;
-  if (a_up == b_up) return 0;
-  const int64_t xlo = std::min(ax, bx), xhi = std::max(ax, bx);
-  if (px < xlo) return 1;
-  if (px >= xhi) return 0;
-  const int64_t c = (ax - px) * (by - py) - (bx - px) * (ay - py);
-  return b_up ? (c > 0) : (c < 0);
-}
-
 struct TooBig {};  // thrown when a cover outgrows the 30-bit entry and cell numbers
 
 struct Child {

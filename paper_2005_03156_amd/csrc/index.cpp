@@ -141,6 +141,64 @@ void build_slabs(const int2* v, int64_t m, const int4& bx, std::vector<int4>& en
   }
 }
 
+// The cell map of one ring (closed: v[0..m], v[m] = v[0]) with box bx: the
+// box cut into kLeafCells x kLeafCells cells of 2^sx x 2^sy units. A cell
+// whose closed rectangle meets an edge of the ring (horizontal and zero-length
+// edges included, tested exactly) is kCellTest. Every other cell holds one
+// answer: the integer points of a cell [x, x + 2^sx) x [y, y + 2^sy) are
+// decided as if nudged by (+e1, +e2) with 0 < e2 << e1 << 1, so they all lie
+// in the open rectangle, which no edge meets. Edge-free cells that share a
+// side share that answer too, so it is taken once per 4-connected group of
+// them, by the crossing rule at the lower-left point of one cell.
+void build_cells(const int2* v, int64_t m, const int4& bx, uint32_t (&cell)[kLeafCells]) {
+  for (uint32_t& c : cell) c = 0xAAAAAAAAu;  // every cell kCellTest
+  const int64_t x0 = bx.x, y0 = bx.z, w = (int64_t)bx.y - bx.x, h = (int64_t)bx.w - bx.z;
+  if (w <= 0 || h <= 0) return;  // an empty box holds no point
+  const int sx = cell_shift((unsigned)w), sy = cell_shift((unsigned)h);
+  constexpr int C = kLeafCells;
+  bool hit[C][C] = {};  // [row][column]: an edge meets the closed cell
+  for (int64_t k = 0; k < m; ++k) {
+    const int64_t ax = v[k].x, ay = v[k].y, bx2 = v[k + 1].x, by2 = v[k + 1].y;
+    // columns c whose closed x-range [x0 + c 2^sx, x0 + (c+1) 2^sx] can meet
+    // the edge's, and likewise rows
+    const int64_t c0 = std::max<int64_t>(0, ((std::min(ax, bx2) - x0) >> sx) - 1);
+    const int64_t c1 = std::min<int64_t>(C - 1, (std::max(ax, bx2) - x0) >> sx);
+    const int64_t r0 = std::max<int64_t>(0, ((std::min(ay, by2) - y0) >> sy) - 1);
+    const int64_t r1 = std::min<int64_t>(C - 1, (std::max(ay, by2) - y0) >> sy);
+    for (int64_t r = r0; r <= r1; ++r)
+      for (int64_t c = c0; c <= c1; ++c)
+        if (!hit[r][c] && seg_meets_square(ax, ay, bx2, by2, x0 + (c << sx), y0 + (r << sy), x0 + ((c + 1) << sx),
+                                            y0 + ((r + 1) << sy)))
+          hit[r][c] = true;
+  }
+  int comp[C][C];
+  for (auto& row : comp)
+    for (int& x : row) x = -1;
+  int todo[C * C];
+  for (int r = 0; r < C; ++r)
+    for (int c = 0; c < C; ++c) {
+      if (hit[r][c] || comp[r][c] >= 0) continue;
+      // the answer of this group: the crossing rule at the cell's lower-left point
+      const int64_t px = x0 + ((int64_t)c << sx), py = y0 + ((int64_t)r << sy);
+      unsigned par = 0;
+      for (int64_t k = 0; k < m; ++k) par ^= crosses_host(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y, px, py);
+      const uint32_t cls = par ? kCellIn : kCellOut;
+      int n = 0;
+      todo[n++] = r * C + c;
+      comp[r][c] = 1;
+      while (n) {
+        const int q = todo[--n], qr = q / C, qc = q % C;
+        cell[qr] = (cell[qr] & ~(3u << (2 * qc))) | (cls << (2 * qc));
+        const int nr[4] = {qr - 1, qr + 1, qr, qr}, nc[4] = {qc, qc, qc - 1, qc + 1};
+        for (int t = 0; t < 4; ++t)
+          if (nr[t] >= 0 && nr[t] < C && nc[t] >= 0 && nc[t] < C && !hit[nr[t]][nc[t]] && comp[nr[t]][nc[t]] < 0) {
+            comp[nr[t]][nc[t]] = 1;
+            todo[n++] = nr[t] * C + nc[t];
+          }
+      }
+    }
+}
+
 }  // namespace
 
 int build_host(const bm_index_desc* d, HostIndex& h) {
@@ -285,6 +343,7 @@ int build_host(const bm_index_desc* d, HostIndex& h) {
       rec.box = bx;
       rec.leaf_id = b;
       build_slabs(ring.data(), m, bx, part[t], rec);
+      build_cells(ring.data(), m, bx, rec.cell);
     }
   };
   {
@@ -422,7 +481,7 @@ int make_device(HostIndex& h, bm_index** out) {
 }
 
 // ---- flat file: magic, scalars, then the arrays
-constexpr char kMagic[8] = {'B', 'M', 'I', 'D', 'X', '0', '0', '2'};
+constexpr char kMagic[8] = {'B', 'M', 'I', 'D', 'X', '0', '0', '3'};
 
 int write_host(const HostIndex& h, const char* path) {
   FILE* f = fopen(path, "wb");

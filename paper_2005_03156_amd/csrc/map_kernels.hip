@@ -118,17 +118,26 @@ __device__ __forceinline__ int4 node_box(const KIndex& ix, int e) {
   return e >= ix.leaf_base ? ix.leaf[e - ix.leaf_base].box : ix.grp[e].box;
 }
 
-// The slab of leaf `leaf` holding height py (py lies in the leaf's y-extent)
-// as a range [first, first + len) of `ent`; also the leaf's block index.
-__device__ __forceinline__ void slab_range(const KIndex& ix, const int leaf, const int py, unsigned& first,
-                                           unsigned& len, unsigned& bid) {
-  const LeafRec* r = reinterpret_cast<const LeafRec*>(reinterpret_cast<const char*>(ix.leaf) + ((unsigned)leaf << 6));
+// Setup of one (leaf, point) pair, p inside the leaf's box: the class of p's
+// cell in the leaf's cell map (kCellOut, kCellIn or kCellTest), the leaf's
+// block index, and for kCellTest the slab holding p.y as a range
+// [first, first + len) of `ent` (len = 0 otherwise). The record's box and
+// header are read first; the cell word and the slab offsets, which depend on
+// them, come from the same 128-byte line.
+__device__ __forceinline__ unsigned pair_setup(const KIndex& ix, const int leaf, const int2 p, unsigned& first,
+                                               unsigned& len, unsigned& bid) {
+  const LeafRec* r = ix.leaf + leaf;  // 128-byte records: leaf << 7 needs more than 32 bits above 2^25 leaves
+  const int4 bx = r->box;
   const int4 meta = *reinterpret_cast<const int4*>(&r->ent);  // ent (2 words, below 2^31), leaf_id, packed
   const unsigned ent = (unsigned)meta.x;
   bid = (unsigned)meta.z;
   const int packed = meta.w;
   const int sh = packed & 0xff, logK = (packed >> 8) & 0xff;
-  const unsigned b = ((unsigned)py - (unsigned)r->box.z) >> sh;
+  const unsigned dy = (unsigned)p.y - (unsigned)bx.z;
+  const unsigned col = ((unsigned)p.x - (unsigned)bx.x) >> cell_shift((unsigned)(bx.y - bx.x));
+  const unsigned row = dy >> cell_shift((unsigned)(bx.w - bx.z));
+  const unsigned cls = (r->cell[row] >> (2u * col)) & 3u;
+  const unsigned b = dy >> sh;
   unsigned o0, o1;
   if (packed & kLeafExtOff) {
     const unsigned nq = ((1u << logK) + 1u + 3u) >> 2;
@@ -140,14 +149,15 @@ __device__ __forceinline__ void slab_range(const KIndex& ix, const int leaf, con
     o1 = r->off[b + 1];
   }
   first = ent + o0;
-  len = o1 - o0;
+  len = cls >= kCellTest ? o1 - o0 : 0u;
+  return cls;
 }
 
 // Crossing parity of a point against one leaf (point inside the leaf box).
 __device__ unsigned leaf_parity(const KIndex& ix, int leaf, int2 p) {
   unsigned first, len, bid;
-  slab_range(ix, leaf, p.y, first, len, bid);
-  unsigned acc = 0;
+  const unsigned cls = pair_setup(ix, leaf, p, first, len, bid);
+  unsigned acc = cls == kCellIn ? 1u : 0u;
   for (unsigned j = 0; j < len; ++j) {
     const int4 e = ix.ent[first + j];
     acc ^= crosses(make_int2(e.x, e.y), make_int2(e.z, e.w), p);
@@ -367,11 +377,13 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
 
 // Crossing-number test on the cnt (leaf, point) pairs of list `cur`, 64 pairs
 // per round; odd pairs atomic-min their block index into the point's slot of
-// S.best. A pair only needs the ring edges listed for the y-slab holding its
-// point (every pair passed the leaf's box test, so the point lies in the
-// ring's y-extent); that list is cut into chunks of kChunk edges and all
-// chunks of the round are dealt across the lanes. The edge list is padded at
-// its end, so a chunk's loads never leave it. All 64 lanes take part.
+// S.best. A pair whose point lies in an In or Out cell of the leaf's cell map
+// is decided by the map (parity 1 or 0) and needs no edges. Any other pair
+// only needs the ring edges listed for the y-slab holding its point (every
+// pair passed the leaf's box test, so the point lies in the ring's
+// y-extent); that list is cut into chunks of kChunk edges and all chunks of
+// the round are dealt across the lanes. The edge list is padded at its end,
+// so a chunk's loads never leave it. All 64 lanes take part.
 template <int kChunkShift>
 __device__ __forceinline__ void pip_rounds(const KIndex& ix, WaveLds& S, const int lane, const int cur,
                                            const unsigned cnt) {
@@ -379,16 +391,16 @@ __device__ __forceinline__ void pip_rounds(const KIndex& ix, WaveLds& S, const i
   for (unsigned r = 0; r < cnt; r += kWave) {
     const unsigned q = r + lane;
     const bool has = q < cnt;
-    unsigned first = 0, len = 0, bid = 0;
+    unsigned first = 0, len = 0, bid = 0, cls = kCellOut;
     const unsigned it = has ? S.item[cur][q] : 0u;
     const int pl = (int)(it & (kTile - 1));
-    if (has) slab_range(ix, (int)(it >> kSlotBits) - ix.leaf_base, S.pts[pl].y, first, len, bid);
+    if (has) cls = pair_setup(ix, (int)(it >> kSlotBits) - ix.leaf_base, S.pts[pl], first, len, bid);
     const unsigned nch = (len + kChunk - 1) >> kChunkShift;
     const unsigned incl = wave_incl_scan(nch, lane);
     const unsigned start = incl - nch;
     const unsigned total = __shfl(incl, kWave - 1);
     S.pair[lane] = make_uint4(first, len, start, (unsigned)pl);
-    S.par[lane] = 0;
+    S.par[lane] = cls == kCellIn ? 1u : 0u;
     for (unsigned w = 0; w < total; w += kCapChunk) {
       const unsigned a = max(start, w), b = min(start + nch, w + (unsigned)kCapChunk);
       for (unsigned c = a; c < b; ++c) S.ch_q[c - w] = (unsigned char)lane;

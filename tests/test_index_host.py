@@ -2,7 +2,8 @@
 bm_index_build_file is parsed here and its derived structures are checked
 against their definitions (half-open boxes, unions, children ranges, slot
 tables as supersets, y-slab edge lists as supersets of the straddling
-edges)."""
+edges, per-leaf cell maps whose In and Out cells hold the oracle's answer at
+every point)."""
 import numpy as np
 import pytest
 
@@ -12,14 +13,15 @@ import synth
 
 GROUP = np.dtype([("box", np.int32, 4), ("child", np.int32, 4)])
 LEAF = np.dtype([("box", np.int32, 4), ("ent", np.int64), ("leaf_id", np.int32), ("packed", np.int32),
-                 ("off", np.uint8, 32)])
+                 ("off", np.uint8, 32), ("cell", np.uint32, 16)])
+assert LEAF.itemsize == 128
 EXT = 1 << 24
 
 
 def read_index(path):
     with open(path, "rb") as f:
         buf = f.read()
-    assert buf[:8] == b"BMIDX002"
+    assert buf[:8] == b"BMIDX003"
     sc = np.frombuffer(buf, np.int32, 12, 8)
     pos = 8 + 48 + 8
     out = {"n_verts": int(np.frombuffer(buf, np.int64, 1, 56)[0])}
@@ -342,3 +344,99 @@ def test_load_rejects_malformed_files(tmp_path):
     for name, data in cases.items():
         rc, msg = load(data)
         assert rc == bm.BM_EIO, (name, rc, msg)
+
+
+# ---- per-leaf cell maps -------------------------------------------------
+
+def cell_shift(w):
+    """The smallest s >= 0 with 16 << s >= w (w >= 1)."""
+    s = 0
+    while (16 << s) < w:
+        s += 1
+    return s
+
+
+def cell_class(rec, px, py):
+    """Class of the cell holding (px, py) in a leaf record: 0 out, 1 in, 2 test."""
+    b = rec["box"]
+    col = (int(px) - int(b[0])) >> cell_shift(int(b[1]) - int(b[0]))
+    row = (int(py) - int(b[2])) >> cell_shift(int(b[3]) - int(b[2]))
+    return (int(rec["cell"][row]) >> (2 * col)) & 3
+
+
+def _rings_file(tmp_path, rings):
+    import paper_2005_03156_amd as bm
+    off = np.concatenate([[0], np.cumsum([len(r) for r in rings])]).astype(np.int64)
+    verts = np.concatenate([np.asarray(r, np.int32) for r in rings])
+    p = str(tmp_path / "rings.bmi")
+    bm.build_index_file(p, off, verts)
+    return off, verts, read_index(p)
+
+
+def test_cell_maps_exact_on_every_point(tmp_path):
+    """Small rings (boxes of 20 to 70 units, so cells are 2 to 8 units a side):
+    every integer point of every In cell is inside its ring and every point of
+    every Out cell outside, by the oracle's crossing test; rings include a
+    comb, a spiral-like notch, a triangle, a square with a long horizontal
+    edge on a cell border and a ring with a zero-length edge."""
+    rng = np.random.default_rng(3)
+    rings = [
+        [(0, 0), (60, 0), (60, 40), (45, 40), (45, 10), (30, 10), (30, 40), (15, 40), (15, 10), (5, 10), (5, 40),
+         (0, 40)],                                                            # comb
+        [(100, 100), (170, 100), (170, 160), (110, 160), (110, 120), (150, 120), (150, 140), (130, 140),
+         (130, 150), (160, 150), (160, 110), (100, 110)],                      # notched spiral
+        [(200, 5), (255, 5), (213, 47)],                                       # triangle
+        [(300, 0), (332, 0), (332, 32), (316, 32), (316, 32), (300, 32)],      # duplicate vertex, border edge
+    ]
+    for _ in range(6):  # random star-shaped rings
+        cx, cy = rng.integers(400, 4000, 2)
+        k = int(rng.integers(5, 14))
+        ang = np.sort(rng.uniform(0, 2 * np.pi, k))
+        rad = rng.uniform(8, 35, k)
+        rings.append(list(zip((cx + rad * np.cos(ang)).round().astype(int), (cy + rad * np.sin(ang)).round().astype(int))))
+    off, verts, ix = _rings_file(tmp_path, rings)
+    L = ix["leaf"]
+    settled = [0, 0]
+    for nb in range(L.shape[0]):
+        rec = L[nb]
+        b = rec["box"]
+        ring = verts[off[rec["leaf_id"]]:off[rec["leaf_id"] + 1]]
+        for py in range(int(b[2]), int(b[3])):
+            for px in range(int(b[0]), int(b[1])):
+                c = cell_class(rec, px, py)
+                if c == 2:
+                    continue
+                settled[c] += 1
+                assert int(oracle.inside(ring, px, py)) == c, (nb, px, py, c)
+    assert settled[0] > 1000 and settled[1] > 1000, settled
+
+
+def test_cell_maps_exact_on_sampled_points(grid221k_index):
+    """220,900-block grid: for 3,000 leaves, points drawn in every In and Out
+    cell (its corners, centre and random points) get the class as their
+    crossing-test answer; and the maps settle a large share of the cells."""
+    g, ix = grid221k_index
+    L = ix["leaf"]
+    rng = np.random.default_rng(11)
+    counts = np.zeros(4, np.int64)
+    for nb in rng.choice(L.shape[0], 3000, replace=False):
+        rec = L[nb]
+        b = [int(v) for v in rec["box"]]
+        sx, sy = cell_shift(b[1] - b[0]), cell_shift(b[3] - b[2])
+        ring = g.verts[g.vert_off[rec["leaf_id"]]:g.vert_off[rec["leaf_id"] + 1]]
+        for r in range(16):
+            for c in range(16):
+                x0, y0 = b[0] + (c << sx), b[2] + (r << sy)
+                x1, y1 = min(b[1], x0 + (1 << sx)), min(b[3], y0 + (1 << sy))
+                if x0 >= x1 or y0 >= y1:
+                    continue
+                cls = (int(rec["cell"][r]) >> (2 * c)) & 3
+                counts[cls] += 1
+                if cls == 2:
+                    continue
+                pts = [(x0, y0), (x1 - 1, y1 - 1), (x0, y1 - 1), (x1 - 1, y0), ((x0 + x1) // 2, (y0 + y1) // 2)]
+                pts += list(zip(rng.integers(x0, x1, 3), rng.integers(y0, y1, 3)))
+                for px, py in pts:
+                    assert int(oracle.inside(ring, int(px), int(py))) == cls, (nb, r, c, px, py)
+    assert counts[3] == 0
+    assert (counts[0] + counts[1]) > 0.5 * counts.sum(), counts
