@@ -92,6 +92,54 @@ def test_extreme_coordinates(torch_cuda, bm):
     assert (got == oracle.brute(g.vert_off, g.verts, pts)).all()
 
 
+def _cell_grid_points(vert_off, verts):
+    """Every corner of every cell of every block's 16 x 16 cell map (cell
+    sides: the smallest powers of two with 16 cells covering each side of the
+    block's box), and the points one unit below and left of each: the
+    borders between cells a crossing test may skip and cells it must run."""
+    box = oracle.ring_boxes(vert_off, verts).astype(np.int64)
+    out = []
+    for x0, x1, y0, y1 in box:
+        if x1 <= x0 or y1 <= y0:
+            continue
+        sx = max(0, int(np.ceil(np.log2(x1 - x0))) - 4) if x1 - x0 > 1 else 0
+        sy = max(0, int(np.ceil(np.log2(y1 - y0))) - 4) if y1 - y0 > 1 else 0
+        xs = np.minimum(x0 + (np.arange(17) << sx), x1)
+        ys = np.minimum(y0 + (np.arange(17) << sy), y1)
+        gx, gy = np.meshgrid(xs, ys)
+        c = np.stack([gx.ravel(), gy.ravel()], 1)
+        out += [c, c - 1, c - [1, 0], c - [0, 1]]
+    return np.concatenate(out).astype(np.int32)
+
+
+def test_cell_map_borders_vs_brute_force(torch_cuda, bm):
+    """Points on the corners of every block's cell map, and one unit off
+    them, for the 1,024-block grid and for rings whose cells are a few units
+    wide (a comb, a notched spiral, a triangle): the mapping kernel, which
+    decides pairs in settled cells from the map, equals brute force."""
+    say("cell map borders")
+    g = synth.geometry("grid1k")
+    pts = _cell_grid_points(g.vert_off, g.verts)
+    ix = bm.Index.from_geometry(g)
+    got = gpu_map(bm, torch_cuda, ix, pts)
+    want = oracle.brute(g.vert_off, g.verts, pts, box_reject=True)
+    assert (got == want).all(), int((got != want).sum())
+    rings = [
+        [(0, 0), (60, 0), (60, 40), (45, 40), (45, 10), (30, 10), (30, 40), (15, 40), (15, 10), (5, 10), (5, 40),
+         (0, 40)],
+        [(100, 100), (170, 100), (170, 160), (110, 160), (110, 120), (150, 120), (150, 140), (130, 140),
+         (130, 150), (160, 150), (160, 110), (100, 110)],
+        [(200, 5), (255, 5), (213, 47)],
+    ]
+    off = np.concatenate([[0], np.cumsum([len(r) for r in rings])]).astype(np.int64)
+    verts = np.concatenate([np.asarray(r, np.int32) for r in rings])
+    ix2 = bm.Index(off, verts)
+    xs, ys = np.meshgrid(np.arange(-2, 260), np.arange(-2, 175))
+    pts2 = np.concatenate([np.stack([xs.ravel(), ys.ravel()], 1), _cell_grid_points(off, verts)]).astype(np.int32)
+    got2 = gpu_map(bm, torch_cuda, ix2, pts2)
+    assert (got2 == oracle.brute(off, verts, pts2)).all()
+
+
 # ------------------------------------------------------------ grid221k ----
 
 @pytest.fixture(scope="module")
