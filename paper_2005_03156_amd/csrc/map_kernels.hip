@@ -784,11 +784,12 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map
 // cache line per 4-byte result: mapping kernel 4.61 -> 3.79 ms per 100M
 // points on the 220,900-block grid, 6.11 -> 4.53 ms per 2^26 points on the
 // 8M-block quadtree without those stores.) Each point's result depends on
-// that point alone, so the order does not change any output. kBB is 5 for an index that fits the last-level cache
-// (shorter sort passes) and 6 for a larger one (finer order, so that the
-// points of one block share a tile and its lines are read from HBM fewer
-// times: 8M-block quadtree 8.19 -> 7.58 ms per 2^26 points with 64 x 64
-// sub-cells in 8,192-point pieces, against 16 x 16 in 2,048).
+// that point alone, so the order does not change any output. kBB is 5 for an
+// index that fits the last-level cache (shorter sort passes) and 6 for a
+// larger one (finer order, so that the points of one block share a tile and
+// its lines are read from HBM fewer times: 8M-block quadtree 8.19 -> 7.58 ms
+// per 2^26 points with 64 x 64 sub-cells in 8,192-point pieces, against 16 x
+// 16 in 2,048).
 template <int kBB>
 struct Bins {
   static constexpr int kN = 1 << (2 * kBB);          // bins

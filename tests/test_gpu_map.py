@@ -720,6 +720,39 @@ def test_server_results_same_alone_and_in_the_mix(torch_cuda, bm, grid221k):
         assert st["mean_requests_per_batch"] > 1.0  # requests really shared batches
 
 
+@pytest.mark.parametrize("threads, direct_log2", [(1, 10), (5, 14), (8, 40)])
+def test_server_pinned_buffers_copy_paths(torch_cuda, bm, grid221k, threads, direct_log2):
+    """Requests and outputs in page-locked memory: pieces of at least
+    direct_min_points are copied by DMA straight to and from their place in
+    the device pool, the others packed and unpacked by `copy_threads` host
+    threads (1: the server's own threads alone). Every request's ids equal
+    those it gets alone, whatever the split."""
+    torch = torch_cuda
+    g, ix, H = grid221k
+    sizes = list(synth.sizes(synth.key("requests20k", 2, 7), 200, 1, 3000.0, 1.5, 200_000))
+    sizes[:6] = [0, 1, 1023, 1024, 16_383, 16_384]
+
+    def pinned(a):
+        t = torch.empty(a.shape, dtype=torch.int32, pin_memory=True)
+        t.numpy()[...] = a
+        return t.numpy()
+    reqs = [pinned(p) for p in _requests(g, sizes, 4)]
+    alone = [gpu_map(bm, torch, ix, p) for p in reqs]
+    cfg = bm.server_cfg(mem_budget_bytes=64 << 20, max_batch_points=150_000, max_slots=4, n_streams=3,
+                        copy_threads=threads, direct_min_points=1 << direct_log2)
+    say("server, pinned buffers", threads, direct_log2)
+    outs = [pinned(np.full(p.shape[0], -7, np.int32)) for p in reqs]
+    srv = bm.Server(ix, cfg)
+    tickets = [srv.submit(p, o) for p, o in zip(reqs, outs)]
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    srv.close()
+    for k, (a, o) in enumerate(zip(alone, outs)):
+        assert (a == o).all(), (k, sizes[k])
+    assert st["completed"] == len(reqs)
+
+
 def test_server_backpressure_timeout_and_failure(torch_cuda, bm, grid221k):
     g, ix, H = grid221k
     pts = _requests(g, [1000, 1000, 1000], 2)
@@ -747,6 +780,10 @@ def test_server_backpressure_timeout_and_failure(torch_cuda, bm, grid221k):
     with pytest.raises(bm.BlockmapError) as e:
         bm.Server(ix, bm.server_cfg(mem_budget_bytes=1000, max_batch_points=1000))
     assert e.value.code == bm.BM_EINVAL
+    for bad in (dict(copy_threads=0), dict(copy_threads=65), dict(direct_min_points=0)):
+        with pytest.raises(bm.BlockmapError) as e:
+            bm.Server(ix, bm.server_cfg(**bad))
+        assert e.value.code == bm.BM_EINVAL, bad
 
 
 def test_server_poisson_trace(torch_cuda, bm, grid221k):
