@@ -409,8 +409,8 @@ typedef struct bm_cover bm_cover;
 
 typedef struct {
   int32_t cell_log2; /* side of the finest (boundary) cells = 2^cell_log2 coordinate units, 1..30;
-                        0 = automatic: about 1/32 of the median block's box side, but no finer
-                        than the total ring length / 2^25 (bounds the number of boundary cells) */
+                        0 = automatic: about 1/64 of the median block's box side, but no finer
+                        than the total ring length / 2^26 (bounds the number of boundary cells) */
   int32_t threads;   /* host threads for the build; 0 = all */
 } bm_cover_cfg;
 
