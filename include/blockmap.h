@@ -117,6 +117,9 @@ typedef struct {
   int32_t n_levels;        /* group levels kept in the index */
   int32_t device;          /* HIP device ordinal holding the index */
   int64_t top_groups;      /* entities on the coarsest level */
+  int32_t sort_bins;       /* bins of the spatial pre-sort (bm_tuning.presort) */
+  int32_t sort_adaptive;   /* 1: those bins adapt to where the blocks are dense (an index over
+                              256 MB); 0: a uniform 32 x 32 or 64 x 64 grid of bins */
 } bm_index_info;
 
 int bm_index_get_info(const bm_index* index, bm_index_info* info);

@@ -42,7 +42,7 @@ class IndexDesc(C.Structure):
 class IndexInfo(C.Structure):
     _fields_ = [("n_blocks", C.c_int64), ("n_vertices", C.c_int64), ("n_nodes", C.c_int64),
                 ("device_bytes", C.c_int64), ("n_levels", C.c_int32), ("device", C.c_int32),
-                ("top_groups", C.c_int64)]
+                ("top_groups", C.c_int64), ("sort_bins", C.c_int32), ("sort_adaptive", C.c_int32)]
 
 
 class Tuning(C.Structure):

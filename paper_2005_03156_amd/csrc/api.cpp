@@ -95,6 +95,8 @@ __attribute__((visibility("default"))) int bm_index_get_info(const bm_index* ix,
   info->n_levels = ix->k.n_levels;
   info->device = ix->device;
   info->top_groups = ix->k.g0;
+  info->sort_adaptive = ix->k.sort_map.cell ? 1 : 0;
+  info->sort_bins = ix->k.sort_map.cell ? ix->k.sort_map.n_bins : 1 << (2 * ix->k.presort_bin_bits);
   return BM_OK;
 }
 

@@ -80,6 +80,26 @@ constexpr long long kMaxEnt = (1ll << 31) - 64;
 constexpr long long kMaxSlotWords = 1ll << 29;    // slot-table words (byte offsets below 2^32)
 constexpr int kEntPad = 16;
 
+// Adaptive sort bins of a large index (built in index.cpp, used by the
+// spatial sort of map_kernels.hip): a 32 x 32 grid of coarse cells over the
+// square of side 2^log_side whose low corner is org; coarse cell c is cut
+// into a 2^d x 2^d grid of bins, d = 0..kSortMaxDepth chosen so that the bins
+// hold about equally many blocks (by box centre), kSortMapBins bins at most,
+// numbered along a Z-curve (coarse cells in Z-order, the bins of a cell in
+// Z-order). cell[c] = first bin | d << 16; sq[bin] = (x0, y0, log side, 0) of
+// the bin's square, as offsets from org.
+constexpr int kSortCoarseBits = 5;
+constexpr int kSortCells = 1 << (2 * kSortCoarseBits);
+constexpr int kSortMapBins = 4096;
+constexpr int kSortMaxDepth = 6;
+struct SortMap {
+  const uint32_t* cell;  // [kSortCells]; null: uniform bins
+  const int4* sq;        // [kSortMapBins]
+  int2 org;
+  int32_t log_side;      // >= kSortCoarseBits + kSortMaxDepth + 6: every bin square is >= 64 wide
+  int32_t n_bins;        // bins in use (host side)
+};
+
 struct KIndex {
   const GroupRec* grp;        // [leaf_base]
   const LeafRec* leaf;        // [n_leaves]
@@ -97,6 +117,7 @@ struct KIndex {
                               // bytes, so 32-bit offsets reach every box a filter step tests
   long long presort_chunk;    // points per spatial-sort chunk (host side)
   int32_t presort_bin_bits;   // bins per axis of the sort: 2^5 or 2^6 (host side)
+  SortMap sort_map;           // with 2^6: the adaptive bins, when the extent allows them
 };
 
 // Cell cover (cover.cpp): a radix trie over non-overlapping square cells of
@@ -153,9 +174,10 @@ struct OffsetHeader {
 // fewer times per point (8M-block quadtree: 10.1 -> 8.4 ms per 2^26 points).
 // The sort's bin grid has 32 x 32 bins for the smaller indexes (each bin then
 // re-sorted by 32 x 32 sub-cells in pieces of 4,096 points; 2,048 / 8,192
-// points: 5.36 / 5.33 ms) and 64 x 64 bins (64 x 64 sub-cells) for the
-// larger ones (the quadtree: 7.58 ms per 2^26 points, against 8.63 with 32 x
-// 32 bins).
+// points: 5.36 / 5.33 ms) and 4,096 bins (64 x 64 sub-cells) for the
+// larger ones: a 64 x 64 grid (the quadtree: 7.58 ms per 2^26 points, against
+// 8.63 with 32 x 32 bins), or the adaptive bins of SortMap when the index's
+// extent allows them.
 constexpr long long kPresortMin = 1 << 20;
 constexpr long long kPresortChunk = 1 << 24;
 constexpr long long kPresortChunkBigIndex = 1 << 26;

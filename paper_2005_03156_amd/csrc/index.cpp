@@ -441,6 +441,76 @@ void free_index(bm_index* ix) {
   delete ix;
 }
 
+// The adaptive sort bins of SortMap: each coarse cell's depth raised, one
+// level at a time, where the most blocks (by box centre) share a bin, while
+// the bins stay within kSortMapBins; false when the extent is too small for
+// bins of at least 64 units, or there are no leaves.
+bool build_sort_map(const HostIndex& h, int& log_side, int& n_bins, std::vector<uint32_t>& cell,
+                    std::vector<int4>& sq) {
+  const int4 rb = h.root_box;
+  if (rb.x >= rb.y || rb.z >= rb.w || h.leaf.empty()) return false;
+  const int64_t ext = std::max<int64_t>((int64_t)rb.y - rb.x, (int64_t)rb.w - rb.z);
+  int L = 0;
+  while (((int64_t)1 << L) < ext) ++L;
+  if (L < kSortCoarseBits + kSortMaxDepth + 6 || L > 31) return false;
+  const int cs = L - kSortCoarseBits;
+  constexpr int kSide = 1 << kSortCoarseBits;
+  std::vector<int64_t> blocks(kSortCells, 0);
+  for (const LeafRec& r : h.leaf)
+    if (r.box.x < r.box.y && r.box.z < r.box.w) {
+      const int64_t x = ((((int64_t)r.box.x + r.box.y - 1) >> 1) - rb.x) >> cs;
+      const int64_t y = ((((int64_t)r.box.z + r.box.w - 1) >> 1) - rb.z) >> cs;
+      blocks[(size_t)(y * kSide + x)]++;
+    }
+  std::vector<int> d(kSortCells, 0);
+  int64_t bins = kSortCells;
+  // max-heap on blocks per bin (blocks / 4^d), ties to the lower cell
+  auto per_bin = [&](int c) { return (double)blocks[c] / (double)((int64_t)1 << (2 * d[c])); };
+  std::vector<std::pair<double, int>> heap;
+  for (int c = 0; c < kSortCells; ++c) heap.push_back({per_bin(c), -c});
+  std::make_heap(heap.begin(), heap.end());
+  while (!heap.empty()) {
+    std::pop_heap(heap.begin(), heap.end());
+    const auto [load, negc] = heap.back();
+    heap.pop_back();
+    const int c = -negc;
+    if (load <= 1.0) break;
+    const int64_t add = 3 * ((int64_t)1 << (2 * d[c]));
+    if (d[c] >= kSortMaxDepth || bins + add > kSortMapBins) continue;
+    d[c]++;
+    bins += add;
+    heap.push_back({per_bin(c), -c});
+    std::push_heap(heap.begin(), heap.end());
+  }
+  // bins in Z-order: coarse cells by Morton index, each cell's bins by theirs
+  auto spread = [](uint32_t v) {
+    uint32_t r = 0;
+    for (int b = 0; b < 16; ++b) r |= ((v >> b) & 1u) << (2 * b);
+    return r;
+  };
+  std::vector<int> zorder(kSortCells);
+  for (int c = 0; c < kSortCells; ++c) zorder[spread((uint32_t)(c % kSide)) | (spread((uint32_t)(c / kSide)) << 1)] = c;
+  cell.assign(kSortCells, 0);
+  sq.assign(kSortMapBins, make_int4(0, 0, 0, 0));
+  uint32_t first = 0;
+  for (int z = 0; z < kSortCells; ++z) {
+    const int c = zorder[z], dc = d[c];
+    cell[c] = first | ((uint32_t)dc << 16);
+    const int fs = cs - dc;  // log side of the cell's bins
+    const uint32_t n = 1u << dc;
+    for (uint32_t fy = 0; fy < n; ++fy)
+      for (uint32_t fx = 0; fx < n; ++fx) {
+        const uint32_t x0 = ((uint32_t)(c % kSide) << cs) + (fx << fs);
+        const uint32_t y0 = ((uint32_t)(c / kSide) << cs) + (fy << fs);
+        sq[first + (spread(fx) | (spread(fy) << 1))] = make_int4((int)x0, (int)y0, fs, 0);
+      }
+    first += n * n;
+  }
+  log_side = L;
+  n_bins = (int)first;
+  return true;
+}
+
 int make_device(HostIndex& h, bm_index** out) {
   bm_index* ix = new (std::nothrow) bm_index();
   if (!ix) return fail(BM_ENOMEM, "bm_index_create: host allocation failed");
@@ -471,6 +541,23 @@ int make_device(HostIndex& h, bm_index** out) {
   k.n_leaves = h.n_leaves;
   k.presort_chunk = ix->bytes > kPresortBigIndex ? kPresortChunkBigIndex : kPresortChunk;
   k.presort_bin_bits = ix->bytes > kPresortBigIndex ? 6 : 5;
+  k.sort_map = SortMap{nullptr, nullptr, make_int2(0, 0), 0, 0};
+  if (k.presort_bin_bits == 6) {
+    int L = 0, nb = 0;
+    std::vector<uint32_t> cell;
+    std::vector<int4> sq;
+    if (build_sort_map(h, L, nb, cell, sq)) {
+      rc = upload(ix, cell, &k.sort_map.cell);
+      if (rc == BM_OK) rc = upload(ix, sq, &k.sort_map.sq);
+      if (rc != BM_OK) {
+        free_index(ix);
+        return rc;
+      }
+      k.sort_map.org = make_int2(h.root_box.x, h.root_box.z);
+      k.sort_map.log_side = L;
+      k.sort_map.n_bins = nb;
+    }
+  }
   ix->n_blocks = h.n_leaves;
   ix->n_nodes = (int64_t)h.parent.size();
   ix->n_verts = h.n_verts;

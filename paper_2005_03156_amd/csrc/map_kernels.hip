@@ -789,7 +789,14 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map
 // larger one (finer order, so that the points of one block share a tile and
 // its lines are read from HBM fewer times: 8M-block quadtree 8.19 -> 7.58 ms
 // per 2^26 points with 64 x 64 sub-cells in 8,192-point pieces, against 16 x
-// 16 in 2,048).
+// 16 in 2,048). A large index's 4,096 bins are adaptive (SortMap: a 32 x 32
+// grid of coarse cells, each cut into 4^d bins where its blocks are dense),
+// and a bin's sub-cells are those of its own square: where blocks are small
+// and points crowd, a uniform bin holds up to millions of a chunk's points,
+// cut into hundreds of pieces that each hold a few points of every block, so
+// a tile touched a block per point (quadtree mapping kernel 4.19 -> 3.68 ms
+// per 2^26-point chunk; the coarse-cell table is read from LDS, so finding the
+// bin costs the sort passes almost nothing).
 template <int kBB>
 struct Bins {
   static constexpr int kN = 1 << (2 * kBB);          // bins
@@ -818,6 +825,37 @@ __device__ __forceinline__ unsigned bin_of(const int2 p, const int4 rb, const in
   const unsigned cx = (unsigned)min(top, max(0ll, dx >> shx));
   const unsigned cy = (unsigned)min(top, max(0ll, dy >> shy));
   return spread6(cx) | (spread6(cy) << 1);
+}
+
+// The adaptive bins (SortMap) of a large index. cell_bin: the bin of p, from
+// the coarse-cell table C (staged in LDS); points outside the square are
+// clamped onto it, as bin_of clamps onto the grid. map_sub_of: p's sub-cell
+// (64 x 64, Morton) of its bin's square sq.
+__device__ __forceinline__ unsigned cell_bin(const int2 p, const uint32_t* __restrict__ C, const SortMap& sm) {
+  const long long top = (1ll << sm.log_side) - 1;
+  const unsigned ox = (unsigned)min(top, max(0ll, (long long)p.x - sm.org.x));
+  const unsigned oy = (unsigned)min(top, max(0ll, (long long)p.y - sm.org.y));
+  const int cs = sm.log_side - kSortCoarseBits;
+  const unsigned e = C[((oy >> cs) << kSortCoarseBits) | (ox >> cs)];
+  const int fs = cs - (int)(e >> 16);
+  const unsigned m = (1u << (e >> 16)) - 1u;
+  return (e & 0xFFFFu) + (spread6((ox >> fs) & m) | (spread6((oy >> fs) & m) << 1));
+}
+
+__device__ __forceinline__ unsigned map_sub_of(const int2 p, const SortMap& sm, const int4 sq) {
+  const long long top = (1ll << sq.z) - 1;
+  const long long dx = (long long)p.x - sm.org.x - (long long)(unsigned)sq.x;
+  const long long dy = (long long)p.y - sm.org.y - (long long)(unsigned)sq.y;
+  const unsigned cx = (unsigned)(min(top, max(0ll, dx)) >> (sq.z - 6));
+  const unsigned cy = (unsigned)(min(top, max(0ll, dy)) >> (sq.z - 6));
+  return spread6(cx) | (spread6(cy) << 1);
+}
+
+// The coarse-cell table in LDS (C[1] and nothing staged for uniform bins).
+template <bool kAd>
+__device__ __forceinline__ void stage_cells(const SortMap& sm, uint32_t* C) {
+  if constexpr (kAd)
+    for (int i = threadIdx.x; i < kSortCells; i += blockDim.x) C[i] = sm.cell[i];
 }
 
 // Exclusive prefix sum over a block of kThreads threads; `wsum` holds one
@@ -851,9 +889,10 @@ __device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* w
 // thread t the points t, t + kBinThreads, ... of that range, and load all of a
 // thread's points before the first LDS atomic, so the loads of a block are in
 // flight together rather than one per loop trip.
-template <int kBB>
+template <int kBB, bool kAd>
 __device__ __forceinline__ void bin_load(const int2* __restrict__ xy, const long long n, const int4 rb,
-                                         const int shx, const int shy, int2 (&p)[kBinPer],
+                                         const int shx, const int shy, const SortMap& sm,
+                                         const uint32_t* __restrict__ C, int2 (&p)[kBinPer],
                                          unsigned (&b)[kBinPer]) {
   const long long lo = (long long)blockIdx.x * kBinBlockPts + threadIdx.x;
 #pragma unroll
@@ -863,24 +902,31 @@ __device__ __forceinline__ void bin_load(const int2* __restrict__ xy, const long
   }
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k)
-    b[k] = lo + (long long)k * kBinThreads < n ? bin_of<kBB>(p[k], rb, shx, shy) : (unsigned)Bins<kBB>::kN;
+    b[k] = lo + (long long)k * kBinThreads < n ? (kAd ? cell_bin(p[k], C, sm) : bin_of<kBB>(p[k], rb, shx, shy))
+                                               : (unsigned)Bins<kBB>::kN;
 }
 
 // Each block counts the bins of its range in LDS and adds the counts to the
 // chunk's per-bin totals.
-template <int kBB>
+template <int kBB, bool kAd>
 __global__ __launch_bounds__(kBinThreads) void bin_count_kernel(const int2* __restrict__ xy, const long long m,
                                                                 const long long chunk, const int4 rb, const int shx,
-                                                                const int shy, unsigned* __restrict__ tot) {
+                                                                const int shy, const SortMap sm,
+                                                                unsigned* __restrict__ tot) {
   constexpr int kNB = Bins<kBB>::kN;
   __shared__ unsigned h[kNB];
+  __shared__ uint32_t C[kAd ? kSortCells : 1];
   const long long c0 = (long long)blockIdx.y * chunk, n = min(chunk, m - c0);
   if ((long long)blockIdx.x * kBinBlockPts >= n) return;
   xy += c0;
   tot += (size_t)blockIdx.y * kBins;
+  if constexpr (kAd) {
+    stage_cells<kAd>(sm, C);
+    __syncthreads();
+  }
   int2 p[kBinPer];
   unsigned b[kBinPer];
-  bin_load<kBB>(xy, n, rb, shx, shy, p, b);
+  bin_load<kBB, kAd>(xy, n, rb, shx, shy, sm, C, p, b);
   for (int i = threadIdx.x; i < kNB; i += kBinThreads) h[i] = 0;
   __syncthreads();
 #pragma unroll
@@ -953,10 +999,11 @@ __global__ __launch_bounds__(1024) void bin_zero_kernel(unsigned* __restrict__ t
 constexpr int kScatPer = 12;
 constexpr long long kScatPts = (long long)kBinThreads * kScatPer;
 
-template <int kBB>
+template <int kBB, bool kAd>
 __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __restrict__ xy, const long long m,
                                                                   const long long chunk, const int4 rb, const int shx,
-                                                                  const int shy, unsigned* __restrict__ cursor,
+                                                                  const int shy, const SortMap sm,
+                                                                  unsigned* __restrict__ cursor,
                                                                   int2* __restrict__ sorted, int* __restrict__ spos,
                                                                   unsigned short* __restrict__ sidx) {
   static_assert(kScatPts <= 65536, "offsets in a scatter block fit 16 bits");
@@ -966,6 +1013,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   __shared__ unsigned h[kNB];  // counts, then first local position of each bin
   __shared__ unsigned d[kNB];  // first position in the chunk minus first local position
   __shared__ unsigned wsum[kBinThreads / kWave];
+  __shared__ uint32_t C[kAd ? kSortCells : 1];
   const long long c0 = (long long)blockIdx.y * chunk, n = min(chunk, m - c0);
   const long long lo = (long long)blockIdx.x * kScatPts;
   if (lo >= n) return;
@@ -974,6 +1022,10 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   sorted += c0;
   spos += c0;
   sidx += c0;
+  if constexpr (kAd) {
+    stage_cells<kAd>(sm, C);
+    __syncthreads();
+  }
   int2 p[kScatPer];
   unsigned b[kScatPer], r[kScatPer];
 #pragma unroll
@@ -983,7 +1035,9 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   }
 #pragma unroll
   for (int k = 0; k < kScatPer; ++k)
-    b[k] = lo + threadIdx.x + (long long)k * kBinThreads < n ? bin_of<kBB>(p[k], rb, shx, shy) : (unsigned)kNB;
+    b[k] = lo + threadIdx.x + (long long)k * kBinThreads < n
+               ? (kAd ? cell_bin(p[k], C, sm) : bin_of<kBB>(p[k], rb, shx, shy))
+               : (unsigned)kNB;
   for (int i = threadIdx.x; i < kNB; i += kBinThreads) h[i] = 0;
   __syncthreads();
 #pragma unroll
@@ -1017,7 +1071,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const int2* __
   const int cnt = (int)min((long long)kScatPts, n - lo);
   for (int j = threadIdx.x; j < cnt; j += kBinThreads) {
     const int2 q = sx[j];
-    const unsigned pos = d[bin_of<kBB>(q, rb, shx, shy)] + (unsigned)j;
+    const unsigned pos = d[kAd ? cell_bin(q, C, sm) : bin_of<kBB>(q, rb, shx, shy)] + (unsigned)j;
     sorted[pos] = q;
     spos[lo + j] = (int)pos;
     sidx[lo + j] = si[j];
@@ -1068,13 +1122,13 @@ __device__ __forceinline__ bool piece_range(const unsigned* __restrict__ cursor,
   return true;
 }
 
-template <int kBB>
+template <int kBB, bool kAd>
 __global__ __launch_bounds__(Bins<kBB>::kRefThreads) void bin_refine_kernel(int2* __restrict__ sorted,
                                                                  unsigned short* __restrict__ rof,
                                                                  const long long chunk,
                                                                  const unsigned* __restrict__ cursor,
                                                                  const unsigned* __restrict__ pstart, const int4 rb,
-                                                                 const int shx, const int shy) {
+                                                                 const int shx, const int shy, const SortMap sm) {
   constexpr int kSubs = Bins<kBB>::kSubs, kRefPer = Bins<kBB>::kRefPer;
   constexpr int kRefThreads = Bins<kBB>::kRefThreads;
   constexpr int kRefPts = kRefThreads * kRefPer;
@@ -1094,6 +1148,7 @@ __global__ __launch_bounds__(Bins<kBB>::kRefThreads) void bin_refine_kernel(int2
   unsigned base;
   int cnt;
   if (!piece_range<kBB>(cursor, pstart, &the_bin, base, cnt)) return;
+  const int4 sq = kAd ? sm.sq[the_bin] : make_int4(0, 0, 0, 0);
   int2 p[kRefPer];
   unsigned key[kRefPer], r[kRefPer];
 #pragma unroll
@@ -1103,7 +1158,9 @@ __global__ __launch_bounds__(Bins<kBB>::kRefThreads) void bin_refine_kernel(int2
   }
 #pragma unroll
   for (int k = 0; k < kRefPer; ++k) {
-    key[k] = threadIdx.x + k * kRefThreads < cnt ? sub_of<kBB>(p[k], rb, shx, shy) : (unsigned)kSubs;
+    key[k] = threadIdx.x + k * kRefThreads < cnt
+                 ? (kAd ? map_sub_of(p[k], sm, sq) : sub_of<kBB>(p[k], rb, shx, shy))
+                 : (unsigned)kSubs;
     r[k] = key[k] < (unsigned)kSubs ? atomicAdd(&h[key[k]], 1u) : 0u;
   }
   __syncthreads();
@@ -1490,32 +1547,59 @@ static unsigned piece_blocks(const long long chunk) {
   return (unsigned)(chunk / ((long long)Bins<kBB>::kRefThreads * Bins<kBB>::kRefPer) + Bins<kBB>::kN);
 }
 
-// One round of sort passes over the nc chunks of m points at p: count, scan,
-// scatter and (when the grid allows) refine.
+constexpr SortMap kNoSortMap{nullptr, nullptr, {0, 0}, 0, 0};
+
+// Does a round refine its bins? Always with adaptive bins (their squares are
+// at least 64 units wide), else when the grid's cells are.
 template <int kBB>
-static void sort_passes(const int4 rb, const int2* p, const long long m, const long long chunk, const unsigned nc,
-                        unsigned* tot, unsigned* cursor, unsigned* pstart, int2* sorted, int* spos,
-                        unsigned short* sidx, unsigned short* rof, hipStream_t stream) {
+static bool refines(const int4 rb, const SortMap& sm) {
+  return sm.cell != nullptr || sort_grid<kBB>(rb).refine;
+}
+
+// One round of sort passes over the nc chunks of m points at p: count, scan,
+// scatter and (when the bins allow) refine; kAd: the index's adaptive bins
+// instead of the uniform grid.
+template <int kBB, bool kAd>
+static void sort_passes_in(const int4 rb, const SortMap& sm, const int2* p, const long long m, const long long chunk,
+                           const unsigned nc, unsigned* tot, unsigned* cursor, unsigned* pstart, int2* sorted,
+                           int* spos, unsigned short* sidx, unsigned short* rof, hipStream_t stream) {
   const SortGrid g = sort_grid<kBB>(rb);
-  hipLaunchKernelGGL(bin_count_kernel<kBB>, dim3((unsigned)((chunk + kBinBlockPts - 1) / kBinBlockPts), nc),
-                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, g.shx, g.shy, tot);
+  const bool refine = kAd || g.refine;
+  hipLaunchKernelGGL((bin_count_kernel<kBB, kAd>), dim3((unsigned)((chunk + kBinBlockPts - 1) / kBinBlockPts), nc),
+                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, g.shx, g.shy, sm, tot);
   hipLaunchKernelGGL(bin_scan_kernel<kBB>, dim3(nc), dim3(kBinThreads), 0, stream, tot, cursor,
-                     g.refine ? pstart : nullptr);
-  hipLaunchKernelGGL(bin_scatter_kernel<kBB>, dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc),
-                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, g.shx, g.shy, cursor, sorted, spos, sidx);
-  if (g.refine)
-    hipLaunchKernelGGL(bin_refine_kernel<kBB>, dim3(piece_blocks<kBB>(chunk), nc), dim3(Bins<kBB>::kRefThreads), 0,
-                       stream, sorted, rof, chunk, cursor, pstart, rb, g.shx, g.shy);
+                     refine ? pstart : nullptr);
+  hipLaunchKernelGGL((bin_scatter_kernel<kBB, kAd>), dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc),
+                     dim3(kBinThreads), 0, stream, p, m, chunk, rb, g.shx, g.shy, sm, cursor, sorted, spos, sidx);
+  if (refine)
+    hipLaunchKernelGGL((bin_refine_kernel<kBB, kAd>), dim3(piece_blocks<kBB>(chunk), nc),
+                       dim3(Bins<kBB>::kRefThreads), 0, stream, sorted, rof, chunk, cursor, pstart, rb, g.shx, g.shy,
+                       sm);
+}
+
+template <int kBB>
+static void sort_passes(const int4 rb, const SortMap& sm, const int2* p, const long long m, const long long chunk,
+                        const unsigned nc, unsigned* tot, unsigned* cursor, unsigned* pstart, int2* sorted, int* spos,
+                        unsigned short* sidx, unsigned short* rof, hipStream_t stream) {
+  if constexpr (kBB == 6) {
+    static_assert(Bins<6>::kN == kSortMapBins, "adaptive bins fill the 64 x 64 grid's bin arrays");
+    if (sm.cell) {
+      sort_passes_in<kBB, true>(rb, sm, p, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof, stream);
+      return;
+    }
+  }
+  sort_passes_in<kBB, false>(rb, sm, p, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof, stream);
 }
 
 // The results of a round (res, in sorted order) back to the points'
 // original positions: unrefine (when the refine pass ran), then unscatter
 // into out.
 template <int kBB>
-static void unsort_passes(const int4 rb, const long long m, const long long chunk, const unsigned nc,
-                          const unsigned* cursor, const unsigned* pstart, const int* spos, const unsigned short* sidx,
-                          const unsigned short* rof, int* res, int* out, hipStream_t stream) {
-  if (sort_grid<kBB>(rb).refine)
+static void unsort_passes(const int4 rb, const SortMap& sm, const long long m, const long long chunk,
+                          const unsigned nc, const unsigned* cursor, const unsigned* pstart, const int* spos,
+                          const unsigned short* sidx, const unsigned short* rof, int* res, int* out,
+                          hipStream_t stream) {
+  if (refines<kBB>(rb, sm))
     hipLaunchKernelGGL(bin_unrefine_kernel<kBB>, dim3(piece_blocks<kBB>(chunk), nc), dim3(Bins<kBB>::kRefThreads), 0,
                        stream, res, rof, chunk, cursor, pstart);
   hipLaunchKernelGGL(unscatter_kernel, dim3((unsigned)((chunk + kScatPts - 1) / kScatPts), nc), dim3(kBinThreads), 0,
@@ -1620,17 +1704,21 @@ static hipError_t launch_presorted(const KIndex& ix, const int32_t* xy, int64_t 
     const unsigned nc = (unsigned)((m + chunk - 1) / chunk);
     mark(2);
     if (ix.presort_bin_bits == 6)
-      sort_passes<6>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof, stream);
+      sort_passes<6>(ix.root_box, ix.sort_map, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof,
+                     stream);
     else
-      sort_passes<5>(ix.root_box, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof, stream);
+      sort_passes<5>(ix.root_box, kNoSortMap, p + s0, m, chunk, nc, tot, cursor, pstart, sorted, spos, sidx, rof,
+                     stream);
     mark(0);
     map_round(sorted, m, res);
     mark(1);
     mark(3);
     if (ix.presort_bin_bits == 6)
-      unsort_passes<6>(ix.root_box, m, chunk, nc, cursor, pstart, spos, sidx, rof, res, out + s0, stream);
+      unsort_passes<6>(ix.root_box, ix.sort_map, m, chunk, nc, cursor, pstart, spos, sidx, rof, res, out + s0,
+                       stream);
     else
-      unsort_passes<5>(ix.root_box, m, chunk, nc, cursor, pstart, spos, sidx, rof, res, out + s0, stream);
+      unsort_passes<5>(ix.root_box, kNoSortMap, m, chunk, nc, cursor, pstart, spos, sidx, rof, res, out + s0,
+                       stream);
     e = hipGetLastError();
   }
   mark(4);

@@ -564,6 +564,42 @@ def test_quadtree8m_one_call_over_several_chunks(torch_cuda, bm, quadtree8m):
     assert (both[2 * CH:].cpu().numpy() == H.map(tail)).all()
 
 
+def test_quadtree8m_adaptive_sort_bins(torch_cuda, bm, quadtree8m):
+    """The 8M-block mesh's index (over 256 MB) sorts over adaptive bins: a
+    32 x 32 grid of coarse cells, each cut into 4^d bins where blocks are
+    dense. A pre-sorted call over points that crowd the mesh's dense part, lie
+    on every possible bin border (and one unit off it) and lie outside the
+    square on every side (clamped into border bins) equals the oracle; the
+    census-scale grid's smaller index keeps the uniform 32 x 32 bins."""
+    torch = torch_cuda
+    g, ix, H = quadtree8m
+    info = ix.info()
+    assert info["sort_adaptive"] == 1 and 1024 < info["sort_bins"] <= 4096, info
+    small = bm.Index.from_geometry(synth.geometry("grid1k")).info()
+    assert small["sort_adaptive"] == 0 and small["sort_bins"] == 1024, small
+    rng = np.random.default_rng(31)
+    W = int(g.W)
+    L = max(W - 1, 1).bit_length()
+    step = 1 << (L - 11)  # the finest bin border spacing (5 coarse bits + depth 6)
+    n_line = 1 << 18
+    lines = rng.integers(0, W // step + 1, n_line) * step + rng.integers(-1, 2, n_line)
+    other = rng.integers(-(1 << 20), W + (1 << 20), n_line)
+    on_x = np.stack([lines, other], 1)
+    on_y = np.stack([other[::-1], lines[::-1]], 1)
+    far = rng.integers(1 << 20, 1 << 28, (1 << 17, 2))
+    outside = np.concatenate([np.stack([-far[:, 0], far[:, 1] % (W + 1)], 1),
+                              np.stack([W + far[:, 0], far[:, 1] % (W + 1)], 1),
+                              np.stack([far[:, 1] % (W + 1), -far[:, 0]], 1),
+                              np.stack([far[:, 1] % (W + 1), W + far[:, 0]], 1)])
+    dense = synth.points("quadtree8m", 1 << 19, i0=123_456_789)
+    pts = np.concatenate([dense, on_x, on_y, outside]).astype(np.int64)
+    pts = np.clip(pts, -(1 << 31), (1 << 31) - 1).astype(np.int32)
+    pts = pts[rng.permutation(len(pts))]
+    say("quadtree8m adaptive bins:", len(pts), "points")
+    got = bm.map_points(ix, torch.from_numpy(pts).cuda()).cpu().numpy()
+    assert (got == H.map(pts)).all()
+
+
 # ------------------------------------------------------- batched form ----
 
 def _cluster_batches(g, sizes, seed):
