@@ -174,7 +174,8 @@ typedef struct {
   int32_t tile_points;      /* batched form: points per unit of work (multiple of 64, <= 2^20) */
   int32_t presort;          /* 1: a call of at least 2^20 points is first sorted along a Z-curve
                                (Morton bins over the index, refined by Morton sub-cells: a
-                               1024 x 1024 grid, or 4096 x 4096 for an index over 256 MB) in
+                               1024 x 1024 grid, or, for an index over 256 MB, 4,096 bins that
+                               are smaller where the blocks are, each cut into 64 x 64) in
                                chunks of 2^24 points (2^26 for an index over 256 MB), so that
                                nearby points are mapped together, and the results, computed in
                                sorted order, are put back in the points' order; it uses
