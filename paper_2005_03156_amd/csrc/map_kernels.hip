@@ -796,14 +796,17 @@ __global__ __launch_bounds__(kBlock, map_min_blocks(kChunkShift)) void batch_map
 // cut into hundreds of pieces that each hold a few points of every block, so
 // a tile touched a block per point (quadtree mapping kernel 4.19 -> 3.68 ms
 // per 2^26-point chunk; the coarse-cell table is read from LDS, so finding the
-// bin costs the sort passes almost nothing).
+// bin costs the sort passes almost nothing). With 64 x 64 sub-cells a piece
+// holds 6,144 points, so that a refine block's LDS (76 KB) lets two run on a
+// CU (8,192-point pieces: sort passes 0.96 -> 1.08 ms, mapping 3.74 -> 3.68
+// ms per quadtree chunk).
 template <int kBB>
 struct Bins {
   static constexpr int kN = 1 << (2 * kBB);          // bins
   static constexpr int kSubBits = kBB == 5 ? 5 : 6;  // per axis
   static constexpr int kSubs = 1 << (2 * kSubBits);  // sub-cells per bin
   static constexpr int kRefThreads = kBB == 5 ? 256 : 512;  // refinement: threads per piece
-  static constexpr int kRefPer = 16;                        // refinement: points per thread
+  static constexpr int kRefPer = kBB == 5 ? 16 : 12;        // refinement: points per thread
 };
 constexpr int kBins = 1 << 12;  // the most bins of any grid: per-chunk stride of the bin arrays
 constexpr int kBinThreads = 1024;  // threads per block of the count and scatter passes
