@@ -277,6 +277,35 @@ def test_spatial_presort_small_root_box(torch_cuda, bm, side):
     assert (a.cpu().numpy()[sub] == oracle.brute(off, verts, pts[sub])).all()
 
 
+def test_large_index_small_extent_uniform_bins(torch_cuda, bm):
+    """An index over 256 MB whose extent is too small for the adaptive sort
+    bins (3.24M squares of side 36 filling a 64,800-unit square) sorts over
+    the uniform 64 x 64 grid of bins: a pre-sorted call equals the squares'
+    closed form (square (i, j), block i * 1800 + j, holds [36 j, 36 j + 36) x
+    [36 i, 36 i + 36)) at every point and brute force on a sample."""
+    torch = torch_cuda
+    n, s = 1800, 36
+    j, i = np.meshgrid(np.arange(n), np.arange(n))
+    x0, y0 = (j.ravel() * s).astype(np.int32), (i.ravel() * s).astype(np.int32)
+    verts = np.stack([np.stack([x0, y0], 1), np.stack([x0 + s, y0], 1), np.stack([x0 + s, y0 + s], 1),
+                      np.stack([x0, y0 + s], 1)], 1).reshape(-1, 2)
+    off = np.arange(0, 4 * n * n + 1, 4, dtype=np.int64)
+    grp = ((i.ravel() // 15) * (n // 15) + j.ravel() // 15).astype(np.int32)
+    say("large index, small extent: building", n * n, "squares")
+    ix = bm.Index(off, verts, [(n // 15) ** 2], [grp])
+    info = ix.info()
+    assert info["device_bytes"] > 256 << 20 and info["sort_adaptive"] == 0 and info["sort_bins"] == 4096, info
+    rng = np.random.default_rng(44)
+    pts = rng.integers(-100, n * s + 100, (1 << 21, 2)).astype(np.int32)
+    got = bm.map_points(ix, torch.from_numpy(pts).cuda()).cpu().numpy()
+    x, y = pts[:, 0].astype(np.int64), pts[:, 1].astype(np.int64)
+    inside = (x >= 0) & (x < n * s) & (y >= 0) & (y < n * s)
+    assert (got == np.where(inside, (y // s) * n + x // s, -1)).all()
+    sub = rng.choice(len(pts), 500, replace=False)
+    assert (got[sub] == oracle.brute(off, verts, pts[sub], box_reject=True)).all()
+    ix.close()
+
+
 def test_grid221k_full_size_every_point(torch_cuda, bm, grid221k):
     """100M points in the benchmark's launch shape: every output equals the
     hierarchy oracle's, the partition property holds at every point (an id
