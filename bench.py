@@ -685,7 +685,8 @@ def bench_quadtree8m(bm, torch, g, ix):
            "map_kernel_ms": lt["kernel_ms"], "sort_ms_per_chunk": lt["sort_ms_per_call"],
            "unsort_ms_per_chunk": lt["unsort_ms_per_call"],
            "end_to_end_points_per_s": N / t_wall, "end_to_end_first_chunk_identical": same,
-           "index_device_bytes": info["device_bytes"],
+           "index_device_bytes": info["device_bytes"], "sort_bins": info["sort_bins"],
+           "sort_bins_adaptive": bool(info["sort_adaptive"]),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": achieved / PEAK_HBM_GBS,
                         "traffic": bpp * launch_pts if bpp is not None else None,
