@@ -29,7 +29,7 @@ constexpr int kTableMaxChildren = 256;  // above this too
 constexpr int kThinFanout = 4;          // group levels with fewer children per group are left out
 constexpr int64_t kMaxRingVerts = (int64_t)1 << 24;       // vertices per ring
 constexpr int64_t kMaxSlabEdges = 4 * kMaxRingVerts + 64;  // the longest slab list such a ring gives
-constexpr int kTableLogSlots = 5;       // slots per axis: 32 (16 for up to 16 children, 8 for up to 8)
+constexpr int kTableLogSlots = 6;       // slots per axis: 64 (16 for up to 16 children, 8 for up to 8)
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 
@@ -47,7 +47,7 @@ inline void grow(int4& a, const int4& b) {
   a.w = std::max(a.w, b.w);
 }
 
-// Slot table of a group with 2..256 children: the group box is cut into S = 32
+// Slot table of a group with 2..256 children: the group box is cut into S = 64
 // equal power-of-two slots per axis (S = 16 for up to 16 children, S = 8 for up
 // to 8, where the table then fills one 128-byte line), and the row of slot s of
 // an axis (W = ceil(children / 64) words) holds a bit for every child whose box

@@ -377,15 +377,15 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
 }
 
 // The root's level-0 boxes and slot table, staged in LDS once per workgroup
-// when they are small (at most 64 level-0 entries and a one-word table: 1.5
-// KB, which leaves room for the 7 workgroups per CU the registers allow).
+// when they are small (at most 64 level-0 entries and a one-word table: 2 KB,
+// which leaves room for the 7 workgroups per CU the registers allow).
 // Every point of every tile starts at the root, so its table rows and boxes
 // then come from LDS rather than from the caches (mapping kernel 3.42 ->
 // 3.24 ms per 100M points on the 220,900-block grid, 4.30 -> 4.19 ms per
 // 2^26 points on the 8M-block quadtree).
 struct RootLds {
   int4 box[64];
-  unsigned long long row[64];  // S x-rows, then S y-rows (S <= 32)
+  unsigned long long row[128];  // S x-rows, then S y-rows (S <= 64)
   int ok;
 };
 
@@ -393,7 +393,7 @@ __device__ __forceinline__ void stage_root(const KIndex& ix, RootLds& R) {
   const int4 rc = ix.root_child;
   const int m = rc.y - rc.x;
   const int logS = rc.w & 0xff;
-  const bool ok = rc.z >= 0 && m >= 1 && m <= 64 && ((unsigned)rc.w >> 24) == 1u && logS <= 5;
+  const bool ok = rc.z >= 0 && m >= 1 && m <= 64 && ((unsigned)rc.w >> 24) == 1u && logS <= 6;
   if (ok) {
     const bool leaves = rc.x >= ix.leaf_base;
     const char* recs = reinterpret_cast<const char*>(ix.grp);

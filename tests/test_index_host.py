@@ -219,7 +219,7 @@ def test_slot_tables_with_several_words_per_row(tmp_path, per_group):
 
 def test_slot_tables_of_small_groups(tmp_path):
     """Groups of up to 8 children get 8 slots per axis, up to 16 get 16, larger
-    ones 32; every table starts on a 128-byte boundary, tables do not overlap,
+    ones 64; every table starts on a 128-byte boundary, tables do not overlap,
     and each is a superset of the children containing a point. 1,024 blocks in
     consecutive groups of 2..40."""
     import paper_2005_03156_amd as bm
@@ -239,8 +239,8 @@ def test_slot_tables_of_small_groups(tmp_path):
     has = child[:, 2] >= 0
     assert np.array_equal(has, m >= 2)
     logS = child[:, 3] & 0xFF
-    assert np.array_equal(logS[has], np.where(m[has] <= 8, 3, np.where(m[has] <= 16, 4, 5)))
-    assert {3, 4, 5} <= set(logS[has].tolist())
+    assert np.array_equal(logS[has], np.where(m[has] <= 8, 3, np.where(m[has] <= 16, 4, 6)))
+    assert {3, 4, 6} <= set(logS[has].tolist())
     off = child[has, 2].astype(np.int64)
     assert np.all(off % 16 == 0)
     span = 2 * (1 << logS[has].astype(np.int64))  # words: one per row (W = 1)
