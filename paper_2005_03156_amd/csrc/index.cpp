@@ -29,7 +29,7 @@ constexpr int kTableMaxChildren = 256;  // above this too
 constexpr int kThinFanout = 4;          // group levels with fewer children per group are left out
 constexpr int64_t kMaxRingVerts = (int64_t)1 << 24;       // vertices per ring
 constexpr int64_t kMaxSlabEdges = 4 * kMaxRingVerts + 64;  // the longest slab list such a ring gives
-constexpr int kTableLogSlots = 6;       // slots per axis: 64 (16 for up to 16 children, 8 for up to 8)
+constexpr int kTableLogSlots = 7;       // slots per axis: 128 (16 for up to 16 children, 8 for up to 8)
 
 const int4 kEmptyBox = {INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 
@@ -47,7 +47,7 @@ inline void grow(int4& a, const int4& b) {
   a.w = std::max(a.w, b.w);
 }
 
-// Slot table of a group with 2..256 children: the group box is cut into S = 64
+// Slot table of a group with 2..256 children: the group box is cut into S = 128
 // equal power-of-two slots per axis (S = 16 for up to 16 children, S = 8 for up
 // to 8, where the table then fills one 128-byte line), and the row of slot s of
 // an axis (W = ceil(children / 64) words) holds a bit for every child whose box
@@ -604,7 +604,7 @@ bool consistent(const HostIndex& h) {
     if (c.z < 0) return true;
     const int logS = c.w & 0xff, shx = (c.w >> 8) & 0xff, shy = (c.w >> 16) & 0xff, m = c.y - c.x;
     const int W = (int)((unsigned)c.w >> 24);
-    if (logS < 3 || logS > 6 || shx > 31 || shy > 31 || m < 1 || m > kTableMaxChildren || W != (m + 63) / 64)
+    if (logS < 3 || logS > 7 || shx > 31 || shy > 31 || m < 1 || m > kTableMaxChildren || W != (m + 63) / 64)
       return false;
     const int64_t S = 1 << logS;
     if ((int64_t)c.z + 2 * S * W > (int64_t)h.slot_mask.size()) return false;

@@ -377,7 +377,7 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
 }
 
 // The root's level-0 boxes and slot table, staged in LDS once per workgroup
-// when they are small (at most 64 level-0 entries and a one-word table: 2 KB,
+// when they are small (at most 64 level-0 entries and a one-word table: 3 KB,
 // which leaves room for the 7 workgroups per CU the registers allow).
 // Every point of every tile starts at the root, so its table rows and boxes
 // then come from LDS rather than from the caches (mapping kernel 3.42 ->
@@ -385,7 +385,7 @@ __device__ __forceinline__ void expand_mixed(const KIndex& ix, WaveLds& S, bool 
 // 2^26 points on the 8M-block quadtree).
 struct RootLds {
   int4 box[64];
-  unsigned long long row[128];  // S x-rows, then S y-rows (S <= 64)
+  unsigned long long row[256];  // S x-rows, then S y-rows (S <= 128)
   int ok;
 };
 
@@ -393,7 +393,7 @@ __device__ __forceinline__ void stage_root(const KIndex& ix, RootLds& R) {
   const int4 rc = ix.root_child;
   const int m = rc.y - rc.x;
   const int logS = rc.w & 0xff;
-  const bool ok = rc.z >= 0 && m >= 1 && m <= 64 && ((unsigned)rc.w >> 24) == 1u && logS <= 6;
+  const bool ok = rc.z >= 0 && m >= 1 && m <= 64 && ((unsigned)rc.w >> 24) == 1u && logS <= 7;
   if (ok) {
     const bool leaves = rc.x >= ix.leaf_base;
     const char* recs = reinterpret_cast<const char*>(ix.grp);

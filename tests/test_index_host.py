@@ -219,7 +219,7 @@ def test_slot_tables_with_several_words_per_row(tmp_path, per_group):
 
 def test_slot_tables_of_small_groups(tmp_path):
     """Groups of up to 8 children get 8 slots per axis, up to 16 get 16, larger
-    ones 64; every table starts on a 128-byte boundary, tables do not overlap,
+    ones 128; every table starts on a 128-byte boundary, tables do not overlap,
     and each is a superset of the children containing a point. 1,024 blocks in
     consecutive groups of 2..40."""
     import paper_2005_03156_amd as bm
@@ -239,8 +239,8 @@ def test_slot_tables_of_small_groups(tmp_path):
     has = child[:, 2] >= 0
     assert np.array_equal(has, m >= 2)
     logS = child[:, 3] & 0xFF
-    assert np.array_equal(logS[has], np.where(m[has] <= 8, 3, np.where(m[has] <= 16, 4, 6)))
-    assert {3, 4, 6} <= set(logS[has].tolist())
+    assert np.array_equal(logS[has], np.where(m[has] <= 8, 3, np.where(m[has] <= 16, 4, 7)))
+    assert {3, 4, 7} <= set(logS[has].tolist())
     off = child[has, 2].astype(np.int64)
     assert np.all(off % 16 == 0)
     span = 2 * (1 << logS[has].astype(np.int64))  # words: one per row (W = 1)
@@ -300,7 +300,7 @@ def test_build_file_rejects_bad_input(tmp_path):
 def test_load_rejects_malformed_files(tmp_path):
     """bm_index_load checks a file before anything reaches the device: a
     truncated file, a wrong magic, a decreasing slab offset, an edge list
-    past the end, a child range past the nodes and a slot table of 2^7 slots
+    past the end, a child range past the nodes and a slot table of 2^8 slots
     all give BM_EIO; the unmodified file passes the checks (on a machine
     without a GPU it then fails only at the upload)."""
     import ctypes as C
@@ -340,7 +340,7 @@ def test_load_rejects_malformed_files(tmp_path):
     t = next(i for i in range(n_grp) if int(ix["child"][i][2]) >= 0)
     bad = bytearray(buf); o = grp_at + 32 * t + 16 + 12
     packed = int(ix["child"][t][3])
-    bad[o:o + 4] = np.int32((packed & ~0xFF) | 7).tobytes(); cases["slot table of 2^7 slots"] = bad
+    bad[o:o + 4] = np.int32((packed & ~0xFF) | 8).tobytes(); cases["slot table of 2^8 slots"] = bad
     for name, data in cases.items():
         rc, msg = load(data)
         assert rc == bm.BM_EIO, (name, rc, msg)
